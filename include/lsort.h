@@ -1,0 +1,193 @@
+/*
+ * lsort -- LearnedSort 2.0 on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the GPU library (liblsort.so).  The method is LearnedSort 2.0
+ * (Kristo, Vaidya, Kraska, arXiv 2107.03290): a two-layer linear eCDF model
+ * trained on a 1% sample predicts each key's bucket (Sec. 2, Sec. 5.1),
+ * keys are partitioned by those predictions (Alg. 1), buckets whose keys
+ * are all equal are never partitioned again (Alg. 2, Sec. 4.2), the rest
+ * are partitioned again and finally sorted inside the bucket, and a touch-up
+ * pass guarantees the order (Alg. 2, last step).
+ *
+ * Conventions for every call:
+ *  - Key buffers are DEVICE memory owned by the caller; they are sorted IN
+ *    PLACE, asynchronously on the given HIP stream (NULL = default stream).
+ *    A call returns once the work is enqueued, except where noted.
+ *  - The library owns its scratch (about one key buffer's worth of device
+ *    memory plus small tables); it grows on first use and is then reused, so
+ *    repeated calls with the same or smaller sizes allocate nothing.
+ *  - Every call returns an ls_status and never throws.  Argument errors are
+ *    reported before any work is enqueued.  ls_last_error() describes the
+ *    most recent failure of a context.
+ *  - A context is not thread-safe: use one per host thread (the server
+ *    below owns its own context).
+ *  - Result: the unique non-decreasing permutation of the input.  u64 keys
+ *    use unsigned order; f64 keys use IEEE-754 totalOrder on the bit
+ *    patterns (-NaN < -inf < ... < -0.0 < +0.0 < ... < +inf < +NaN), so the
+ *    output is bit-exact and independent of every tuning parameter.
+ */
+#ifndef LSORT_H
+#define LSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* ls_stream_t;   /* a hipStream_t */
+
+typedef enum {
+    LS_OK = 0,
+    LS_ERR_INVALID = 1,      /* bad argument (null pointer with n > 0, bad dtype, bad offsets, bad params) */
+    LS_ERR_NOMEM = 2,        /* device or host allocation failed */
+    LS_ERR_HIP = 3,          /* a HIP runtime call failed */
+    LS_ERR_UNSUPPORTED = 4,  /* parameter combination not supported */
+    LS_ERR_BUDGET = 5,       /* server: a request larger than the whole HBM budget */
+    LS_ERR_TIMEOUT = 6,      /* server: wait timed out */
+    LS_ERR_NOTFOUND = 7      /* server: unknown ticket */
+} ls_status;
+
+typedef enum { LS_F64 = 1, LS_U64 = 2 } ls_dtype;
+
+/* ls_params.flags */
+#define LS_FLAG_DEBUG_TOUCHUP  0x1u   /* check every adjacent pair after the sort, not only bucket seams */
+#define LS_FLAG_SYNC           0x2u   /* wait for the stream before returning */
+#define LS_FLAG_NONMONOTONE    0x4u   /* test hook: perturb predictions so buckets overlap; the touch-up must repair */
+#define LS_FLAG_PROFILE        0x8u   /* time each kernel class with HIP events (read with ls_last_profile) */
+
+/* Tuning parameters (Sec. 5.1 gives f = 1000, c = 100, L = 1000, 1% sample).
+ * Zero fields take the library defaults.  None of them changes the result. */
+typedef struct {
+    uint32_t struct_size;      /* sizeof(ls_params) */
+    uint32_t fanout;           /* f: buckets per partition, 2..4096 (default 1024) */
+    uint32_t leaves;           /* L: leaf models of the two-layer model, 1..1024 (default 1024) */
+    uint32_t tile;             /* keys staged per partition tile in LDS (default 2048) */
+    uint32_t base_threshold;   /* buckets of at most this many keys are sorted in LDS (default 4096, max 8192) */
+    uint32_t flags;            /* LS_FLAG_* */
+    double   sample_rate;      /* model training sample (default 0.01) */
+    uint64_t sample_cap;       /* upper bound on one model's sample, 0 = none */
+    uint64_t seed;             /* seed of the counter-based sampler */
+} ls_params;
+
+typedef struct ls_ctx ls_ctx;
+
+/* Device status bits returned by ls_sync. */
+#define LS_DEV_SEAM_REPAIRED   0x1u   /* the touch-up found an out-of-order seam and repaired it */
+#define LS_DEV_FALLBACK        0x2u   /* a bucket needed the highest-differing-bit split (no model progress) */
+#define LS_DEV_DEEP            0x4u   /* recursion went deeper than two levels */
+
+/* Create a context on HIP device `device` (the device becomes current). */
+ls_status ls_create(ls_ctx** out, int device);
+ls_status ls_destroy(ls_ctx* ctx);
+
+/* Fill *p with the defaults. */
+void ls_default_params(ls_params* p);
+
+/* Device bytes of scratch a sort of n keys needs (upper estimate). */
+ls_status ls_workspace_size(ls_ctx* ctx, ls_dtype dtype, size_t n, const ls_params* p, size_t* bytes);
+
+/* Allocate scratch for sorts of up to n keys ahead of time. */
+ls_status ls_reserve(ls_ctx* ctx, size_t n, const ls_params* p);
+
+/* Sort n keys of d_keys in place (Alg. 2).  d_keys: device pointer to n
+ * contiguous 8-byte keys, 8-byte aligned.  p may be NULL (defaults). */
+ls_status ls_sort_f64(ls_ctx* ctx, double* d_keys, size_t n, ls_stream_t stream, const ls_params* p);
+ls_status ls_sort_u64(ls_ctx* ctx, uint64_t* d_keys, size_t n, ls_stream_t stream, const ls_params* p);
+
+/* Sort many independent arrays in one batched pipeline.  d_keys holds the
+ * segments back to back; h_offsets (HOST memory, num_segments + 1 entries,
+ * non-decreasing, h_offsets[0] = 0) gives each segment's key range.
+ * h_dtypes (HOST, num_segments entries of ls_dtype values) may be NULL, in
+ * which case every segment has type `dtype`.  Each segment ends up sorted
+ * exactly as a separate ls_sort_* call would sort it. */
+ls_status ls_sort_segments(ls_ctx* ctx, ls_dtype dtype, void* d_keys, const uint64_t* h_offsets,
+                           size_t num_segments, const uint8_t* h_dtypes, ls_stream_t stream,
+                           const ls_params* p);
+
+/* One array of a batch: its own device buffer, length and key type. */
+typedef struct {
+    void*    d_keys;
+    uint64_t n;
+    uint32_t dtype;            /* ls_dtype */
+    uint32_t reserved;
+} ls_array;
+
+/* Sort `count` separate device arrays together (the segmented pipeline
+ * without the shared buffer).  h_arrays is HOST memory. */
+ls_status ls_sort_arrays(ls_ctx* ctx, const ls_array* h_arrays, size_t count, ls_stream_t stream,
+                         const ls_params* p);
+
+/* Wait for the context's last sort and report device status bits
+ * (LS_DEV_*); device_status may be NULL. */
+ls_status ls_sync(ls_ctx* ctx, uint32_t* device_status);
+
+/* Counters of the last completed sort (filled by ls_sync):
+ * [0] partition rounds, [1] tasks partitioned, [2] LDS base-case groups,
+ * [3] all-equal buckets filled without sorting, [4] keys in those buckets,
+ * [5] fallback splits, [6] out-of-order seams repaired, [7] deepest level. */
+ls_status ls_last_stats(ls_ctx* ctx, uint64_t* out8);
+
+/* Per kernel class, accumulated since the last ls_profile_reset (only for
+ * sorts run with LS_FLAG_PROFILE): out[3*k + 0] milliseconds, [3*k + 1]
+ * launches, [3*k + 2] algorithmic bytes (keys read + written as the method
+ * requires).  Classes k: 0 train, 1 histogram, 2 scan, 3 classify,
+ * 4 scatter, 5 base case, 6 fill, 7 touch-up.  cap >= 24. */
+ls_status ls_last_profile(ls_ctx* ctx, double* out, size_t cap);
+ls_status ls_profile_reset(ls_ctx* ctx);
+
+const char* ls_status_string(ls_status s);
+const char* ls_last_error(ls_ctx* ctx);
+
+/* ---- stage hooks for parity checks against a reference implementation ---- */
+
+/* Train the global model on the 1% sample of d_keys[0..n) (Sec. 5.1) and
+ * copy it to h_model_out (HOST, cap doubles) in the layout
+ * [xmin, xmax, rs, m'] + per leaf [X_k, y_k, yhi_k, s_k] (4 + 4L doubles;
+ * an empty leaf has X_k = +inf).  Synchronous. */
+ls_status ls_model_train(ls_ctx* ctx, ls_dtype dtype, const void* d_keys, size_t n,
+                         const ls_params* p, double* h_model_out, size_t cap);
+
+/* One partition histogram (Alg. 1 bucket sizes S_B plus per-bucket
+ * min/max of the order-preserving key words) of d_keys[0..n) with a model
+ * given in the layout above (HOST, `leaves` leaves): bucket of x is
+ * clamp(floor(F(x) * scale) - offset, 0, fanout - 1).  Outputs are HOST
+ * arrays of `fanout` entries; empty buckets report min = ~0, max = 0.
+ * Synchronous. */
+ls_status ls_stage_hist(ls_ctx* ctx, ls_dtype dtype, const void* d_keys, size_t n,
+                        const double* h_model, uint32_t leaves, double scale, int64_t offset,
+                        uint32_t fanout, uint64_t* h_counts, uint64_t* h_min, uint64_t* h_max);
+
+/* ---- serving: continuous batching of sort requests ---- */
+
+typedef struct ls_server ls_server;
+
+/* Start a server on `device` that admits requests while the device memory
+ * they need (keys already resident + the library's scratch) stays within
+ * hbm_budget_bytes, batches the admitted ones into segmented sorts, and
+ * keeps up to max_inflight batches in flight on separate streams.  p may be
+ * NULL. */
+ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
+                           uint32_t max_inflight, const ls_params* p);
+
+/* Queue a request: sort d_keys (device, n keys of dtype) in place.  Returns
+ * immediately with a ticket.  A request that can never fit the budget is
+ * rejected with LS_ERR_BUDGET; one that fits later waits in the queue. */
+ls_status ls_server_submit(ls_server* s, ls_dtype dtype, void* d_keys, size_t n, uint64_t* ticket);
+
+/* Wait for a ticket (timeout_ms < 0: forever).  latency_s receives the time
+ * from submission to completion on the device clock of the host. */
+ls_status ls_server_wait(ls_server* s, uint64_t ticket, int timeout_ms, double* latency_s);
+
+/* Server counters: [0] submitted, [1] completed, [2] batches, [3] peak
+ * admitted bytes, [4] currently admitted bytes, [5] queued requests. */
+ls_status ls_server_stats(ls_server* s, uint64_t* out6);
+
+/* Drain every request and stop. */
+ls_status ls_server_destroy(ls_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,805 @@
+// Host side of the LearnedSort 2.0 pipeline and the C ABI (include/lsort.h).
+//
+// One sort (or one batch of arrays) runs as:
+//   train   global models on a sample of each large array (Sec. 5.1),
+//   rounds  histogram -> scan -> classify -> scatter over every task of the
+//           round (Alg. 1 as a count-then-place partition), the host reading
+//           back only the next round's task list,
+//   finish  LDS base case over the groups of small buckets, fills of the
+//           all-equal buckets, touch-up seam check (Alg. 2).
+#include "lsort.h"
+#include "lsort_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lsort;
+
+namespace {
+
+constexpr uint32_t kTargetChunks = 2048;
+constexpr uint32_t kDefaultFanout = 1024;
+constexpr uint32_t kDefaultLeaves = 1024;
+constexpr uint32_t kDefaultTile = 2048;
+constexpr uint32_t kDefaultBase = 4096;
+constexpr uint64_t kDefaultSeed = 0x2107032900000001ull;
+constexpr uint32_t kLocalMinSample = 1024;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct Params {
+    uint32_t fanout, leaves, tile, base, flags;
+    double rate;
+    uint64_t cap, seed;
+};
+
+struct Array {
+    uint64_t* keys;
+    uint64_t* scratch;
+    uint64_t n;
+    uint32_t dtype;
+};
+
+uint64_t mix_host(uint64_t z)
+{
+    // Stafford's Mix13 finaliser: decorrelates local-model seeds.
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+uint64_t sample_size(uint64_t n, double rate, uint64_t cap)
+{
+    double want = std::ceil(rate * (double)n);
+    uint64_t m = want < 1.0 ? 1u : (uint64_t)want;
+    if (cap && m > cap)
+        m = cap;
+    return m;
+}
+
+}  // namespace
+
+struct ls_ctx {
+    int device = 0;
+    std::string err;
+    DevBuf scratch, models, sample, minmax, lcnt, lmin, jobs, tasks, next, cnt, pos, scantmp, bstat, skip,
+        tflags, groups, fills, ctl;
+    RoundCtl* h_ctl = nullptr;       // pinned readback
+    RoundCtl* h_ctl_init = nullptr;  // pinned upload
+    uint64_t stats[8] = {0};
+    uint32_t dev_status = 0;
+    size_t lds_limit = 65536;
+    // LS_FLAG_PROFILE: event pairs around each kernel class
+    double prof_ms[8] = {0}, prof_launch[8] = {0}, prof_bytes[8] = {0};
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+};
+
+namespace {
+
+ls_status fail(ls_ctx* C, ls_status s, const std::string& msg)
+{
+    if (C)
+        C->err = msg;
+    return s;
+}
+
+#define HIPCHECK(C, expr)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((C), LS_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_));     \
+    } while (0)
+
+// Grow a device buffer; queued work may still use the old one, so wait first.
+ls_status ensure(ls_ctx* C, DevBuf& b, size_t bytes, hipStream_t st, size_t keep = 0)
+{
+    if (bytes <= b.cap && b.p)
+        return LS_OK;
+    size_t nb = std::max(bytes, b.cap + b.cap / 2);
+    nb = std::max<size_t>(nb, 256);
+    void* np = nullptr;
+    if (hipMalloc(&np, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(C, LS_ERR_NOMEM, "device allocation of " + std::to_string(nb) + " bytes failed");
+    }
+    HIPCHECK(C, hipStreamSynchronize(st));
+    if (keep && b.p)
+        HIPCHECK(C, hipMemcpy(np, b.p, std::min(keep, b.cap), hipMemcpyDeviceToDevice));
+    if (b.p)
+        HIPCHECK(C, hipFree(b.p));
+    b.p = np;
+    b.cap = nb;
+    return LS_OK;
+}
+
+// Event pairs for one kernel class; read back after the next stream sync.
+struct Prof {
+    ls_ctx* C;
+    hipStream_t st;
+    bool on;
+    struct Rec {
+        int k;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    hipEvent_t ev()
+    {
+        if (C->ev_used == C->ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess)
+                return nullptr;
+            C->ev_pool.push_back(e);
+        }
+        return C->ev_pool[C->ev_used++];
+    }
+    void begin(int k)
+    {
+        if (!on)
+            return;
+        Rec r{k, ev(), ev(), 0.0};
+        if (r.a && r.b && hipEventRecord(r.a, st) == hipSuccess)
+            recs.push_back(r);
+    }
+    void end(double bytes)
+    {
+        if (!on || recs.empty())
+            return;
+        recs.back().bytes = bytes;
+        (void)hipEventRecord(recs.back().b, st);
+    }
+    // after a stream sync
+    void collect()
+    {
+        for (auto& r : recs) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                C->prof_ms[r.k] += ms;
+                C->prof_launch[r.k] += 1;
+                C->prof_bytes[r.k] += r.bytes;
+            }
+        }
+        recs.clear();
+        C->ev_used = 0;
+    }
+};
+
+#define TRY(expr)                       \
+    do {                                \
+        ls_status s_ = (expr);          \
+        if (s_ != LS_OK)                \
+            return s_;                  \
+    } while (0)
+
+ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
+{
+    P.fanout = kDefaultFanout;
+    P.leaves = kDefaultLeaves;
+    P.tile = kDefaultTile;
+    P.base = kDefaultBase;
+    P.flags = 0;
+    P.rate = 0.01;
+    P.cap = 0;
+    P.seed = kDefaultSeed;
+    if (p) {
+        if (p->struct_size != sizeof(ls_params))
+            return fail(C, LS_ERR_INVALID, "ls_params.struct_size mismatch");
+        if (p->fanout) P.fanout = p->fanout;
+        if (p->leaves) P.leaves = p->leaves;
+        if (p->tile) P.tile = p->tile;
+        if (p->base_threshold) P.base = p->base_threshold;
+        P.flags = p->flags;
+        if (p->sample_rate != 0.0) P.rate = p->sample_rate;
+        P.cap = p->sample_cap;
+        if (p->seed) P.seed = p->seed;
+    }
+    if (P.fanout < 2 || P.fanout > kMaxFanout)
+        return fail(C, LS_ERR_INVALID, "fanout must be in [2, 4096]");
+    if (P.leaves < 1 || P.leaves > kMaxLeaves)
+        return fail(C, LS_ERR_INVALID, "leaves must be in [1, 1024]");
+    if (P.tile != 1024 && P.tile != 2048 && P.tile != 4096)
+        return fail(C, LS_ERR_INVALID, "tile must be 1024, 2048 or 4096");
+    if (P.base < 2 || P.base > kMaxBase)
+        return fail(C, LS_ERR_INVALID, "base_threshold must be in [2, 8192]");
+    if (!(P.rate > 0.0) || P.rate > 1.0)
+        return fail(C, LS_ERR_INVALID, "sample_rate must be in (0, 1]");
+    size_t scatter_lds = (size_t)P.tile * 10 + (size_t)P.fanout * 16 + 32 + (size_t)P.leaves * 34 + 64;
+    size_t hist_lds = (size_t)P.fanout * 20 + 32 + (size_t)P.leaves * 34 + 64;
+    if (scatter_lds > C->lds_limit || hist_lds > C->lds_limit)
+        return fail(C, LS_ERR_UNSUPPORTED, "tile/fanout/leaves exceed the LDS of one workgroup");
+    return LS_OK;
+}
+
+struct Trainer {
+    std::vector<ModelJob> jobs;
+    uint64_t samples = 0, leaves = 0, models = 0;
+    uint32_t blocks = 0;
+
+    uint64_t add(const uint64_t* src, uint64_t n, uint64_t m, uint64_t seed, uint32_t L, uint32_t dtype,
+                 uint64_t model_base)
+    {
+        ModelJob J;
+        J.src = src;
+        J.n = n;
+        J.m = m;
+        J.seed = seed;
+        J.sample_off = samples;
+        J.model_off = model_base + models;
+        J.leaf_off = leaves;
+        J.leaves = L;
+        J.dtype = dtype;
+        J.block0 = blocks;
+        J.nblocks = (uint32_t)((m + 2047) / 2048);
+        samples += m;
+        leaves += L;
+        models += model_doubles(L);
+        blocks += J.nblocks;
+        jobs.push_back(J);
+        return J.model_off;
+    }
+};
+
+ls_status run_training(ls_ctx* C, Trainer& T, uint64_t model_base, hipStream_t st, Prof* prof = nullptr)
+{
+    if (T.jobs.empty())
+        return LS_OK;
+    TRY(ensure(C, C->models, (model_base + T.models) * sizeof(double), st, model_base * sizeof(double)));
+    TRY(ensure(C, C->sample, T.samples * 8, st));
+    TRY(ensure(C, C->minmax, T.jobs.size() * 16, st));
+    TRY(ensure(C, C->lcnt, T.leaves * 4, st));
+    TRY(ensure(C, C->lmin, T.leaves * 8, st));
+    TRY(ensure(C, C->jobs, T.jobs.size() * sizeof(ModelJob), st));
+    HIPCHECK(C, hipMemcpyAsync(C->jobs.p, T.jobs.data(), T.jobs.size() * sizeof(ModelJob), hipMemcpyHostToDevice, st));
+    if (prof)
+        prof->begin(0);
+    HIPCHECK(C, launch_train((const ModelJob*)C->jobs.p, (uint32_t)T.jobs.size(), T.blocks, (uint64_t*)C->sample.p,
+                             (uint64_t*)C->minmax.p, (uint32_t*)C->lcnt.p, (uint64_t*)C->lmin.p,
+                             (double*)C->models.p, st));
+    if (prof)
+        prof->end((double)T.samples * 16.0);
+    // the job table is reused by the next training call: keep it alive
+    HIPCHECK(C, hipStreamSynchronize(st));
+    if (prof)
+        prof->collect();
+    return LS_OK;
+}
+
+// The whole pipeline for a batch of arrays.  msd_only: partition on the
+// order-preserving bits alone (the touch-up repair path).
+ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, bool msd_only,
+                       bool* repaired)
+{
+    uint64_t total = 0;
+    for (auto& a : arrays)
+        total += a.n;
+    TRY(ensure(C, C->scratch, std::max<uint64_t>(total, 1) * 8, st));
+    {
+        uint64_t off = 0;
+        for (auto& a : arrays) {
+            a.scratch = (uint64_t*)C->scratch.p + off;
+            off += a.n;
+        }
+    }
+    TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
+    std::vector<Group> groups0;
+    std::vector<Task> tasks;
+    Trainer tr;
+    uint32_t lf = 31u - (uint32_t)__builtin_clz(P.fanout);
+    for (uint32_t i = 0; i < arrays.size(); ++i) {
+        const Array& a = arrays[i];
+        if (a.n <= 1)
+            continue;
+        if (a.n <= P.base) {
+            groups0.push_back(Group{a.keys, a.keys, 0, (uint32_t)a.n, a.dtype});
+            continue;
+        }
+        Task t{};
+        t.keys = a.keys;
+        t.scratch = a.scratch;
+        t.start = 0;
+        t.n = a.n;
+        t.dtype = a.dtype;
+        t.src = 0;
+        t.level = 0;
+        t.seg = i;
+        if (msd_only) {
+            t.kind = kMsd;
+            t.fanout = 1u << lf;
+            t.shift = 64 - lf;
+        } else {
+            uint64_t m = sample_size(a.n, P.rate, P.cap);
+            t.kind = kGlobal;
+            t.fanout = P.fanout;
+            t.scale = (double)P.fanout;
+            t.offset = 0;
+            t.leaves = P.leaves;
+            t.model = tr.add(a.keys, a.n, m, P.seed, P.leaves, a.dtype, 0);
+        }
+        tasks.push_back(t);
+    }
+    const uint64_t global_models = tr.models;
+    Prof prof{C, st, (P.flags & LS_FLAG_PROFILE) != 0, {}};
+    TRY(run_training(C, tr, 0, st, &prof));
+
+    // cumulative lists
+    uint64_t ngroups = groups0.size(), nfill = 0;
+    uint64_t group0_keys = 0;
+    for (auto& g : groups0)
+        group0_keys += g.n;
+    std::memset(C->h_ctl, 0, sizeof(RoundCtl));
+    TRY(ensure(C, C->groups, std::max<uint64_t>(ngroups, 1) * sizeof(Group), st));
+    if (ngroups)
+        HIPCHECK(C, hipMemcpyAsync(C->groups.p, groups0.data(), ngroups * sizeof(Group), hipMemcpyHostToDevice, st));
+    std::memset(C->h_ctl_init, 0, sizeof(RoundCtl));
+    C->h_ctl_init->ngroups = (uint32_t)ngroups;
+    HIPCHECK(C, hipMemcpyAsync(C->ctl.p, C->h_ctl_init, sizeof(RoundCtl), hipMemcpyHostToDevice, st));
+    HIPCHECK(C, hipStreamSynchronize(st));   // h_ctl_init is reused below
+
+    uint64_t rounds = 0, ntasks_total = 0;
+    uint32_t max_level = 0;
+    const uint32_t flags = msd_only ? 0u : (P.flags & LS_FLAG_NONMONOTONE);
+    while (!tasks.empty()) {
+        ++rounds;
+        ntasks_total += tasks.size();
+        // layout of the round: chunks, bucket table, count matrix
+        uint64_t Nr = 0;
+        for (auto& t : tasks)
+            Nr += t.n;
+        uint64_t chunk = (Nr + kTargetChunks - 1) / kTargetChunks;
+        chunk = std::max<uint64_t>(P.tile * 4ull, (chunk + P.tile - 1) / P.tile * P.tile);
+        uint64_t E = 0, base = 0;
+        uint32_t chunks = 0, buckets = 0, max_f = 2, max_L = 1;
+        for (auto& t : tasks) {
+            t.nchunks = (uint32_t)((t.n + chunk - 1) / chunk);
+            t.chunk0 = chunks;
+            t.bucket_off = buckets;
+            t.cnt_off = E;
+            t.cnt_base = base;
+            chunks += t.nchunks;
+            buckets += t.fanout;
+            E += (uint64_t)t.fanout * t.nchunks;
+            base += t.n;
+            max_f = std::max(max_f, t.fanout);
+            if (t.kind != kMsd)
+                max_L = std::max(max_L, t.leaves);
+            max_level = std::max(max_level, t.level);
+        }
+        const uint32_t nt = (uint32_t)tasks.size();
+        TRY(ensure(C, C->tasks, nt * sizeof(Task), st));
+        TRY(ensure(C, C->cnt, E * 4, st));
+        TRY(ensure(C, C->pos, E * 8, st));
+        TRY(ensure(C, C->scantmp, scan_tmp_entries(E) * 8, st));
+        TRY(ensure(C, C->bstat, (uint64_t)buckets * 16, st));
+        TRY(ensure(C, C->skip, buckets, st));
+        TRY(ensure(C, C->tflags, nt * 4, st));
+        TRY(ensure(C, C->next, (uint64_t)buckets * sizeof(Task), st));
+        TRY(ensure(C, C->groups, (ngroups + buckets) * sizeof(Group), st, ngroups * sizeof(Group)));
+        TRY(ensure(C, C->fills, (nfill + buckets + Nr / kFillPiece + 1) * sizeof(Fill), st, nfill * sizeof(Fill)));
+        HIPCHECK(C, hipMemcpyAsync(C->tasks.p, tasks.data(), nt * sizeof(Task), hipMemcpyHostToDevice, st));
+        HIPCHECK(C, hipMemsetAsync(C->ctl.p, 0, sizeof(uint32_t), st));   // ntasks = 0
+        const RoundCtl before = *C->h_ctl;
+        HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, buckets, st));
+        prof.begin(1);
+        HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, chunks, chunk, (const double*)C->models.p,
+                                (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, max_f, max_L, flags, st));
+        prof.end((double)Nr * 8.0);
+        prof.begin(2);
+        HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, E, (uint64_t*)C->scantmp.p, st));
+        prof.end((double)E * 16.0);
+        prof.begin(3);
+        HIPCHECK(C, launch_classify((const Task*)C->tasks.p, nt, (const uint64_t*)C->pos.p,
+                                    (const uint64_t*)C->bstat.p, P.base, P.fanout, (Task*)C->next.p,
+                                    (Group*)C->groups.p, (Fill*)C->fills.p, (uint8_t*)C->skip.p,
+                                    (uint32_t*)C->tflags.p, (RoundCtl*)C->ctl.p, max_f, st));
+        prof.end((double)buckets * 32.0);
+        prof.begin(4);
+        HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, chunks, chunk, (const double*)C->models.p,
+                                   (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
+                                   (const uint32_t*)C->tflags.p, P.tile, max_f, max_L, flags, st));
+        prof.end(0.0);
+        HIPCHECK(C, hipMemcpyAsync(C->h_ctl, C->ctl.p, sizeof(RoundCtl), hipMemcpyDeviceToHost, st));
+        HIPCHECK(C, hipStreamSynchronize(st));
+        if (prof.on && !prof.recs.empty()) {
+            // scatter: reads every key of a task that progressed, writes those not in all-equal buckets
+            const double moved = (double)(Nr - (C->h_ctl->stall_keys - before.stall_keys));
+            const double kept = moved - (double)(C->h_ctl->fillkeys - before.fillkeys);
+            prof.recs.back().bytes = 8.0 * moved + 8.0 * kept;
+        }
+        prof.collect();
+        const uint32_t nnext = C->h_ctl->ntasks;
+        ngroups = C->h_ctl->ngroups;
+        nfill = C->h_ctl->nfill;
+        tasks.resize(nnext);
+        if (nnext)
+            HIPCHECK(C, hipMemcpy(tasks.data(), C->next.p, nnext * sizeof(Task), hipMemcpyDeviceToHost));
+        // local models for the next round
+        Trainer lt;
+        for (auto& t : tasks) {
+            if (t.kind != kLocal)
+                continue;
+            uint64_t m = std::max<uint64_t>(std::min<uint64_t>(t.n, kLocalMinSample), sample_size(t.n, P.rate, 0));
+            if (P.cap && m > P.cap)
+                m = std::max<uint64_t>(P.cap, std::min<uint64_t>(t.n, kLocalMinSample));
+            uint32_t L = (uint32_t)std::min<uint64_t>(P.leaves, m);
+            uint64_t seed = mix_host(P.seed ^ mix_host(t.start + 0x9e3779b97f4a7c15ull * (t.level + 1)) ^
+                                     ((uint64_t)t.seg << 32));
+            const uint64_t* src = (t.src ? t.scratch : t.keys) + t.start;
+            t.leaves = L;
+            t.model = lt.add(src, t.n, m, seed, L, t.dtype, global_models);
+        }
+        TRY(run_training(C, lt, global_models, st, &prof));
+    }
+    // finish: LDS base case, all-equal fills, touch-up
+    const double gkeys = (double)C->h_ctl->group_keys + (double)group0_keys;
+    const double fkeys = (double)C->h_ctl->fillkeys;
+    prof.begin(5);
+    HIPCHECK(C, launch_base((const Group*)C->groups.p, (uint32_t)ngroups, P.base, st));
+    prof.end(16.0 * gkeys);
+    prof.begin(6);
+    HIPCHECK(C, launch_fill((const Fill*)C->fills.p, (uint32_t)nfill, st));
+    prof.end(8.0 * fkeys);
+    prof.begin(7);
+    HIPCHECK(C, launch_touchup((const Group*)C->groups.p, (uint32_t)ngroups, (const Fill*)C->fills.p,
+                               (uint32_t)nfill, (P.flags & LS_FLAG_DEBUG_TOUCHUP) ? 1 : 0, (RoundCtl*)C->ctl.p, st));
+    prof.end(16.0 * (double)(ngroups + nfill));
+    HIPCHECK(C, hipMemcpyAsync(C->h_ctl, C->ctl.p, sizeof(RoundCtl), hipMemcpyDeviceToHost, st));
+    HIPCHECK(C, hipStreamSynchronize(st));
+    prof.collect();
+    RoundCtl fin = *C->h_ctl;
+    C->stats[0] = rounds;
+    C->stats[1] = ntasks_total;
+    C->stats[2] = ngroups;
+    C->stats[3] = fin.nfillbuckets;
+    C->stats[4] = fin.fillkeys;
+    C->stats[5] = fin.fallbacks;
+    C->stats[6] = fin.violations;
+    C->stats[7] = max_level;
+    if (fin.fallbacks)
+        C->dev_status |= LS_DEV_FALLBACK;
+    if (max_level > 1)
+        C->dev_status |= LS_DEV_DEEP;
+    if (fin.violations) {
+        if (msd_only)
+            return fail(C, LS_ERR_HIP, "touch-up found out-of-order seams after the repair pass");
+        // Touch-up repair: the model put keys out of order (only possible
+        // with the test hook); re-partition on the key bits alone.
+        uint64_t saved[8];
+        std::memcpy(saved, C->stats, sizeof saved);
+        TRY(run_pipeline(C, arrays, st, P, true, nullptr));
+        std::memcpy(C->stats, saved, sizeof saved);
+        C->dev_status |= LS_DEV_SEAM_REPAIRED;
+        if (repaired)
+            *repaired = true;
+    }
+    return LS_OK;
+}
+
+ls_status sort_arrays(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const ls_params* p)
+{
+    Params P;
+    TRY(resolve(C, p, P));
+    for (auto& a : arrays) {
+        if (a.n && !a.keys)
+            return fail(C, LS_ERR_INVALID, "null key pointer with n > 0");
+        if (a.dtype != LS_F64 && a.dtype != LS_U64)
+            return fail(C, LS_ERR_INVALID, "unknown dtype");
+        if (((uintptr_t)a.keys) & 7u)
+            return fail(C, LS_ERR_INVALID, "key buffer must be 8-byte aligned");
+    }
+    HIPCHECK(C, hipSetDevice(C->device));
+    C->dev_status = 0;
+    std::memset(C->stats, 0, sizeof C->stats);
+    return run_pipeline(C, arrays, st, P, false, nullptr);
+}
+
+}  // namespace
+
+extern "C" {
+
+void ls_default_params(ls_params* p)
+{
+    if (!p)
+        return;
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(ls_params);
+    p->fanout = kDefaultFanout;
+    p->leaves = kDefaultLeaves;
+    p->tile = kDefaultTile;
+    p->base_threshold = kDefaultBase;
+    p->sample_rate = 0.01;
+    p->seed = kDefaultSeed;
+}
+
+ls_status ls_create(ls_ctx** out, int device)
+{
+    if (!out)
+        return LS_ERR_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return LS_ERR_INVALID;
+    if (hipSetDevice(device) != hipSuccess)
+        return LS_ERR_HIP;
+    ls_ctx* C = new (std::nothrow) ls_ctx();
+    if (!C)
+        return LS_ERR_NOMEM;
+    C->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+        C->lds_limit = prop.sharedMemPerBlock;
+    if (hipHostMalloc((void**)&C->h_ctl, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&C->h_ctl_init, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess) {
+        delete C;
+        return LS_ERR_NOMEM;
+    }
+    *out = C;
+    return LS_OK;
+}
+
+ls_status ls_destroy(ls_ctx* C)
+{
+    if (!C)
+        return LS_ERR_INVALID;
+    (void)hipSetDevice(C->device);
+    (void)hipDeviceSynchronize();
+    DevBuf* bufs[] = {&C->scratch, &C->models, &C->sample, &C->minmax, &C->lcnt, &C->lmin, &C->jobs,
+                      &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat, &C->skip,
+                      &C->tflags, &C->groups, &C->fills, &C->ctl};
+    for (DevBuf* b : bufs)
+        if (b->p)
+            (void)hipFree(b->p);
+    if (C->h_ctl)
+        (void)hipHostFree(C->h_ctl);
+    if (C->h_ctl_init)
+        (void)hipHostFree(C->h_ctl_init);
+    for (hipEvent_t e : C->ev_pool)
+        (void)hipEventDestroy(e);
+    delete C;
+    return LS_OK;
+}
+
+ls_status ls_workspace_size(ls_ctx* C, ls_dtype dtype, size_t n, const ls_params* p, size_t* bytes)
+{
+    if (!C || !bytes || (dtype != LS_F64 && dtype != LS_U64))
+        return LS_ERR_INVALID;
+    Params P;
+    TRY(resolve(C, p, P));
+    size_t chunks = kTargetChunks + 64;
+    size_t tables = (size_t)P.fanout * chunks * 12 + (size_t)P.fanout * 64 + model_doubles(P.leaves) * 8 * 4;
+    size_t lists = (n / 2 + P.fanout) * (sizeof(Group) + sizeof(Fill)) / 8;
+    *bytes = n * 8 + tables + lists + (n / 50 + 4096) * 8;
+    return LS_OK;
+}
+
+ls_status ls_reserve(ls_ctx* C, size_t n, const ls_params* p)
+{
+    if (!C)
+        return LS_ERR_INVALID;
+    Params P;
+    TRY(resolve(C, p, P));
+    HIPCHECK(C, hipSetDevice(C->device));
+    return ensure(C, C->scratch, std::max<size_t>(n, 1) * 8, nullptr);
+}
+
+ls_status ls_sort_f64(ls_ctx* C, double* d_keys, size_t n, ls_stream_t stream, const ls_params* p)
+{
+    if (!C)
+        return LS_ERR_INVALID;
+    std::vector<Array> a{Array{(uint64_t*)d_keys, nullptr, n, LS_F64}};
+    return sort_arrays(C, a, (hipStream_t)stream, p);
+}
+
+ls_status ls_sort_u64(ls_ctx* C, uint64_t* d_keys, size_t n, ls_stream_t stream, const ls_params* p)
+{
+    if (!C)
+        return LS_ERR_INVALID;
+    std::vector<Array> a{Array{d_keys, nullptr, n, LS_U64}};
+    return sort_arrays(C, a, (hipStream_t)stream, p);
+}
+
+ls_status ls_sort_segments(ls_ctx* C, ls_dtype dtype, void* d_keys, const uint64_t* h_offsets,
+                           size_t num_segments, const uint8_t* h_dtypes, ls_stream_t stream,
+                           const ls_params* p)
+{
+    if (!C)
+        return LS_ERR_INVALID;
+    if (num_segments && !h_offsets)
+        return fail(C, LS_ERR_INVALID, "null offsets");
+    if (num_segments && h_offsets[0] != 0)
+        return fail(C, LS_ERR_INVALID, "offsets[0] must be 0");
+    std::vector<Array> a;
+    a.reserve(num_segments);
+    for (size_t i = 0; i < num_segments; ++i) {
+        if (h_offsets[i + 1] < h_offsets[i])
+            return fail(C, LS_ERR_INVALID, "offsets must be non-decreasing");
+        uint32_t dt = h_dtypes ? h_dtypes[i] : (uint32_t)dtype;
+        uint64_t n = h_offsets[i + 1] - h_offsets[i];
+        if (n && !d_keys)
+            return fail(C, LS_ERR_INVALID, "null key pointer with keys to sort");
+        a.push_back(Array{(uint64_t*)d_keys + h_offsets[i], nullptr, n, dt});
+    }
+    return sort_arrays(C, a, (hipStream_t)stream, p);
+}
+
+ls_status ls_sort_arrays(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_stream_t stream,
+                         const ls_params* p)
+{
+    if (!C)
+        return LS_ERR_INVALID;
+    if (count && !h_arrays)
+        return fail(C, LS_ERR_INVALID, "null array list");
+    std::vector<Array> a;
+    a.reserve(count);
+    for (size_t i = 0; i < count; ++i)
+        a.push_back(Array{(uint64_t*)h_arrays[i].d_keys, nullptr, h_arrays[i].n, h_arrays[i].dtype});
+    return sort_arrays(C, a, (hipStream_t)stream, p);
+}
+
+ls_status ls_sync(ls_ctx* C, uint32_t* device_status)
+{
+    if (!C)
+        return LS_ERR_INVALID;
+    HIPCHECK(C, hipSetDevice(C->device));
+    HIPCHECK(C, hipDeviceSynchronize());
+    if (device_status)
+        *device_status = C->dev_status;
+    return LS_OK;
+}
+
+ls_status ls_last_stats(ls_ctx* C, uint64_t* out8)
+{
+    if (!C || !out8)
+        return LS_ERR_INVALID;
+    std::memcpy(out8, C->stats, sizeof C->stats);
+    return LS_OK;
+}
+
+ls_status ls_last_profile(ls_ctx* C, double* out, size_t cap)
+{
+    if (!C || !out || cap < 24)
+        return LS_ERR_INVALID;
+    for (int k = 0; k < 8; ++k) {
+        out[3 * k] = C->prof_ms[k];
+        out[3 * k + 1] = C->prof_launch[k];
+        out[3 * k + 2] = C->prof_bytes[k];
+    }
+    return LS_OK;
+}
+
+ls_status ls_profile_reset(ls_ctx* C)
+{
+    if (!C)
+        return LS_ERR_INVALID;
+    for (int k = 0; k < 8; ++k)
+        C->prof_ms[k] = C->prof_launch[k] = C->prof_bytes[k] = 0;
+    return LS_OK;
+}
+
+const char* ls_status_string(ls_status s)
+{
+    switch (s) {
+    case LS_OK: return "ok";
+    case LS_ERR_INVALID: return "invalid argument";
+    case LS_ERR_NOMEM: return "out of memory";
+    case LS_ERR_HIP: return "HIP runtime error";
+    case LS_ERR_UNSUPPORTED: return "unsupported parameters";
+    case LS_ERR_BUDGET: return "request exceeds the memory budget";
+    case LS_ERR_TIMEOUT: return "timed out";
+    case LS_ERR_NOTFOUND: return "unknown ticket";
+    }
+    return "unknown status";
+}
+
+const char* ls_last_error(ls_ctx* C)
+{
+    return C ? C->err.c_str() : "null context";
+}
+
+// ---------------------------------------------------------------- stage hooks
+
+ls_status ls_model_train(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n, const ls_params* p,
+                         double* h_model_out, size_t cap)
+{
+    if (!C || !d_keys || !n || !h_model_out || (dtype != LS_F64 && dtype != LS_U64))
+        return LS_ERR_INVALID;
+    Params P;
+    TRY(resolve(C, p, P));
+    if (cap < 4 + 4 * (size_t)P.leaves)
+        return fail(C, LS_ERR_INVALID, "model output buffer too small");
+    HIPCHECK(C, hipSetDevice(C->device));
+    Trainer tr;
+    tr.add((const uint64_t*)d_keys, n, sample_size(n, P.rate, P.cap), P.seed, P.leaves, dtype, 0);
+    TRY(run_training(C, tr, 0, nullptr));
+    std::vector<double> dev(model_doubles(P.leaves));
+    HIPCHECK(C, hipMemcpy(dev.data(), C->models.p, dev.size() * 8, hipMemcpyDeviceToHost));
+    const uint32_t L = P.leaves;
+    for (int i = 0; i < 4; ++i)
+        h_model_out[i] = dev[i];
+    for (uint32_t k = 0; k < L; ++k) {
+        h_model_out[4 + 4 * k + 0] = dev[4 + k];
+        h_model_out[4 + 4 * k + 1] = dev[4 + L + k];
+        h_model_out[4 + 4 * k + 2] = dev[4 + 2 * L + k];
+        h_model_out[4 + 4 * k + 3] = dev[4 + 3 * L + k];
+    }
+    return LS_OK;
+}
+
+ls_status ls_stage_hist(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n, const double* h_model,
+                        uint32_t leaves, double scale, int64_t offset, uint32_t fanout, uint64_t* h_counts,
+                        uint64_t* h_min, uint64_t* h_max)
+{
+    if (!C || !d_keys || !n || !h_model || !h_counts || (dtype != LS_F64 && dtype != LS_U64))
+        return LS_ERR_INVALID;
+    if (leaves < 1 || leaves > kMaxLeaves || fanout < 2 || fanout > kMaxFanout)
+        return fail(C, LS_ERR_INVALID, "leaves or fanout out of range");
+    HIPCHECK(C, hipSetDevice(C->device));
+    hipStream_t st = nullptr;
+    // model: export layout -> device layout with the previous-knot table
+    std::vector<double> dev(model_doubles(leaves), 0.0);
+    for (int i = 0; i < 4; ++i)
+        dev[i] = h_model[i];
+    uint32_t* prev = reinterpret_cast<uint32_t*>(dev.data() + 4 + 4 * (size_t)leaves);
+    uint32_t last = kNoPrev;
+    for (uint32_t k = 0; k < leaves; ++k) {
+        double X = h_model[4 + 4 * k];
+        dev[4 + k] = X;
+        dev[4 + leaves + k] = h_model[4 + 4 * k + 1];
+        dev[4 + 2 * leaves + k] = h_model[4 + 4 * k + 2];
+        dev[4 + 3 * leaves + k] = h_model[4 + 4 * k + 3];
+        prev[k] = last;
+        if (!std::isinf(X))
+            last = k;
+    }
+    TRY(ensure(C, C->models, dev.size() * 8, st));
+    HIPCHECK(C, hipMemcpy(C->models.p, dev.data(), dev.size() * 8, hipMemcpyHostToDevice));
+    const uint32_t tile = kDefaultTile;
+    uint64_t chunk = std::max<uint64_t>(tile * 4ull, ((n + kTargetChunks - 1) / kTargetChunks + tile - 1) / tile * tile);
+    Task t{};
+    t.keys = (uint64_t*)d_keys;
+    t.scratch = nullptr;
+    t.start = 0;
+    t.n = n;
+    t.model = 0;
+    t.scale = scale;
+    t.offset = offset;
+    t.fanout = fanout;
+    t.kind = kGlobal;
+    t.dtype = dtype;
+    t.src = 0;
+    t.leaves = leaves;
+    t.nchunks = (uint32_t)((n + chunk - 1) / chunk);
+    t.chunk0 = 0;
+    t.bucket_off = 0;
+    t.cnt_off = 0;
+    TRY(ensure(C, C->tasks, sizeof(Task), st));
+    TRY(ensure(C, C->cnt, (size_t)fanout * t.nchunks * 4, st));
+    TRY(ensure(C, C->bstat, (size_t)fanout * 16, st));
+    HIPCHECK(C, hipMemcpy(C->tasks.p, &t, sizeof(Task), hipMemcpyHostToDevice));
+    HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, fanout, st));
+    HIPCHECK(C, launch_hist((const Task*)C->tasks.p, 1, t.nchunks, chunk, (const double*)C->models.p,
+                            (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, fanout, leaves, 0, st));
+    HIPCHECK(C, hipDeviceSynchronize());
+    std::vector<uint32_t> cnt((size_t)fanout * t.nchunks);
+    std::vector<uint64_t> bs((size_t)fanout * 2);
+    HIPCHECK(C, hipMemcpy(cnt.data(), C->cnt.p, cnt.size() * 4, hipMemcpyDeviceToHost));
+    HIPCHECK(C, hipMemcpy(bs.data(), C->bstat.p, bs.size() * 8, hipMemcpyDeviceToHost));
+    for (uint32_t b = 0; b < fanout; ++b) {
+        uint64_t s = 0;
+        for (uint32_t c = 0; c < t.nchunks; ++c)
+            s += cnt[(size_t)b * t.nchunks + c];
+        h_counts[b] = s;
+        if (h_min) h_min[b] = bs[2 * b];
+        if (h_max) h_max[b] = bs[2 * b + 1];
+    }
+    return LS_OK;
+}
+
+}  // extern "C"

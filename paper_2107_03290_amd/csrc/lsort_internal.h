@@ -1,0 +1,123 @@
+// Internal structures shared by the HIP kernels and the host pipeline.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsort {
+
+constexpr uint32_t kF64 = 1;
+constexpr uint32_t kU64 = 2;
+
+constexpr uint32_t kMaxFanout = 4096;
+constexpr uint32_t kMaxLeaves = 1024;
+constexpr uint32_t kMaxBase = 8192;        // largest group the LDS base case sorts
+constexpr uint32_t kNoPrev = 0xffffu;      // "no knot below": F = 0
+constexpr uint64_t kFillPiece = 1u << 16;  // keys per fill work item
+
+// How a task maps a key to a bucket.
+enum TaskKind : uint32_t {
+    kGlobal = 0,     // level 0: floor(F * f), F the array's model
+    kGlobalL1 = 1,   // level 1 under parent i: floor(F * f^2) - i*f (same model)
+    kLocal = 2,      // deeper: floor(F_local * f), model trained on the range
+    kMsd = 3,        // no model progress: digit of the order-preserving word
+};
+
+// A key range that still has to be partitioned.
+struct Task {
+    uint64_t* keys;       // the array's final buffer (caller's)
+    uint64_t* scratch;    // the array's scratch buffer (same length)
+    uint64_t start;       // first key of the range, relative to the array
+    uint64_t n;           // keys in the range
+    uint64_t model;       // offset (in doubles) of the model in the model pool
+    double scale;         // kGlobal / kLocal: f; kGlobalL1: f*f
+    int64_t offset;       // kGlobalL1: i*f
+    uint32_t fanout;
+    uint32_t kind;        // TaskKind
+    uint32_t dtype;       // kF64 / kU64
+    uint32_t src;         // 0: keys live in `keys`, 1: in `scratch`
+    uint32_t leaves;      // leaves of the model
+    uint32_t shift;       // kMsd: bucket = (ord >> shift) & (fanout - 1)
+    uint32_t level;
+    uint32_t chunk0;      // first chunk of this task in the round
+    uint32_t nchunks;
+    uint32_t bucket_off;  // first bucket of this task in the round's bucket table
+    uint64_t cnt_off;     // first entry of this task in the round's count matrix
+    uint64_t cnt_base;    // sum of the sizes of the round's earlier tasks
+    uint32_t seg;
+    uint32_t pad;
+};
+
+// A run of adjacent small buckets sorted by one workgroup in LDS.
+struct Group {
+    const uint64_t* src;
+    uint64_t* dst;
+    uint64_t start;       // of dst, relative to its array (0: no seam to check)
+    uint32_t n;
+    uint32_t dtype;
+};
+
+// Part of an all-equal bucket: written with its single value, never sorted.
+struct Fill {
+    uint64_t* dst;
+    uint64_t raw;
+    uint64_t start;       // relative to the array
+    uint32_t n;
+    uint32_t dtype;
+};
+
+// One model to train: sample m keys of src[0..n) and fit L leaves.
+struct ModelJob {
+    const uint64_t* src;
+    uint64_t n;
+    uint64_t m;
+    uint64_t seed;
+    uint64_t sample_off;  // into the sample buffer
+    uint64_t model_off;   // into the model pool (doubles)
+    uint64_t leaf_off;    // into the leaf-statistics tables
+    uint32_t leaves;
+    uint32_t dtype;
+    uint32_t block0;      // first sampling block of this job
+    uint32_t nblocks;
+};
+
+// Counters the classify kernel appends to; read by the host after a round.
+struct RoundCtl {
+    uint32_t ntasks;      // next-round tasks
+    uint32_t ngroups;     // base-case groups (cumulative)
+    uint32_t nfill;       // fill items (cumulative)
+    uint32_t nfillbuckets;
+    uint64_t fillkeys;
+    uint32_t fallbacks;
+    uint32_t violations;  // out-of-order seams found by the touch-up
+    uint64_t group_keys;  // keys in base-case groups (cumulative)
+    uint64_t stall_keys;  // keys of tasks that made no progress (not scattered)
+};
+
+inline size_t model_doubles(uint32_t L) { return 4 + 4 * (size_t)L + (L + 1) / 2; }
+
+// Kernel launchers (lsort_kernels.hip).
+hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks,
+                        uint64_t* d_sample, uint64_t* d_minmax, uint32_t* d_lcnt, uint64_t* d_lmin,
+                        double* d_models, hipStream_t st);
+hipError_t launch_round_init(uint64_t* d_bstat, uint32_t nbuckets, hipStream_t st);
+hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
+                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint32_t max_fanout,
+                       uint32_t max_leaves, uint32_t flags, hipStream_t st);
+hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, hipStream_t st);
+size_t scan_tmp_entries(uint64_t n);
+hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t* d_pos,
+                           const uint64_t* d_bstat, uint32_t base_cap, uint32_t param_fanout,
+                           Task* d_next, Group* d_groups, Fill* d_fills, uint8_t* d_skip,
+                           uint32_t* d_task_flags, RoundCtl* d_ctl, uint32_t max_fanout, hipStream_t st);
+hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
+                          const double* d_models, const uint64_t* d_pos, const uint8_t* d_skip,
+                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout,
+                          uint32_t max_leaves, uint32_t flags, hipStream_t st);
+hipError_t launch_base(const Group* d_groups, uint32_t ngroups, uint32_t base_cap, hipStream_t st);
+hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, hipStream_t st);
+hipError_t launch_touchup(const Group* d_groups, uint32_t ngroups, const Fill* d_fills, uint32_t nfill,
+                          int full, RoundCtl* d_ctl, hipStream_t st);
+
+
+}  // namespace lsort
