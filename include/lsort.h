@@ -64,7 +64,7 @@ typedef struct {
     uint32_t fanout;           /* f: buckets per partition, 2..4096 (default 1024) */
     uint32_t leaves;           /* L: leaf models of the two-layer model, 1..1024 (default 1024) */
     uint32_t tile;             /* keys staged per partition tile in LDS (default 2048) */
-    uint32_t base_threshold;   /* buckets of at most this many keys are sorted in LDS (default 4096, max 8192) */
+    uint32_t base_threshold;   /* buckets of at most this many keys are sorted in LDS, in groups of < 2x (default 4096, max 4096) */
     uint32_t flags;            /* LS_FLAG_* */
     double   sample_rate;      /* model training sample (default 0.01) */
     uint64_t sample_cap;       /* upper bound on one model's sample, 0 = none */

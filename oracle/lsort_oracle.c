@@ -191,8 +191,11 @@ static int model_train(model_t* M, const uint64_t* sample, uint64_t m, uint32_t 
         if (sample[t] > hi) hi = sample[t];
     }
     M->mfin = mfin;
-    if (mfin == 0)
-        return ORC_OK;               /* every F = 0: the caller falls back */
+    if (mfin == 0) {                 /* no knot at all: every F = 0 */
+        for (uint32_t k = 0; k < L; ++k)
+            M->X[k] = INFINITY;
+        return ORC_OK;
+    }
     M->xmin = ord_value(lo, dtype);
     M->xmax = ord_value(hi, dtype);
     M->rs = (M->xmax > M->xmin) ? (double)L / (M->xmax - M->xmin) : 0.0;

@@ -207,12 +207,12 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
         return fail(C, LS_ERR_INVALID, "leaves must be in [1, 1024]");
     if (P.tile != 1024 && P.tile != 2048 && P.tile != 4096)
         return fail(C, LS_ERR_INVALID, "tile must be 1024, 2048 or 4096");
-    if (P.base < 2 || P.base > kMaxBase)
-        return fail(C, LS_ERR_INVALID, "base_threshold must be in [2, 8192]");
+    if (P.base < 2 || 2 * P.base > kMaxBase)
+        return fail(C, LS_ERR_INVALID, "base_threshold must be in [2, 4096]");
     if (!(P.rate > 0.0) || P.rate > 1.0)
         return fail(C, LS_ERR_INVALID, "sample_rate must be in (0, 1]");
-    size_t scatter_lds = (size_t)P.tile * 10 + (size_t)P.fanout * 16 + 32 + (size_t)P.leaves * 34 + 64;
-    size_t hist_lds = (size_t)P.fanout * 20 + 32 + (size_t)P.leaves * 34 + 64;
+    size_t scatter_lds = (((size_t)P.tile * 10 + (size_t)P.fanout * 16 + 15) & ~(size_t)15) + model_lds_bytes(P.leaves) + 128;
+    size_t hist_lds = (((size_t)P.fanout * 20 + 15) & ~(size_t)15) + model_lds_bytes(P.leaves) + 64;
     if (scatter_lds > C->lds_limit || hist_lds > C->lds_limit)
         return fail(C, LS_ERR_UNSUPPORTED, "tile/fanout/leaves exceed the LDS of one workgroup");
     return LS_OK;
@@ -297,7 +297,7 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         const Array& a = arrays[i];
         if (a.n <= 1)
             continue;
-        if (a.n <= P.base) {
+        if (a.n <= 2ull * P.base) {
             groups0.push_back(Group{a.keys, a.keys, 0, (uint32_t)a.n, a.dtype});
             continue;
         }
@@ -441,7 +441,7 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
     const double gkeys = (double)C->h_ctl->group_keys + (double)group0_keys;
     const double fkeys = (double)C->h_ctl->fillkeys;
     prof.begin(5);
-    HIPCHECK(C, launch_base((const Group*)C->groups.p, (uint32_t)ngroups, P.base, st));
+    HIPCHECK(C, launch_base((const Group*)C->groups.p, (uint32_t)ngroups, 2 * P.base, st));
     prof.end(16.0 * gkeys);
     prof.begin(6);
     HIPCHECK(C, launch_fill((const Fill*)C->fills.p, (uint32_t)nfill, st));
@@ -724,10 +724,10 @@ ls_status ls_model_train(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n
     for (int i = 0; i < 4; ++i)
         h_model_out[i] = dev[i];
     for (uint32_t k = 0; k < L; ++k) {
-        h_model_out[4 + 4 * k + 0] = dev[4 + k];
-        h_model_out[4 + 4 * k + 1] = dev[4 + L + k];
-        h_model_out[4 + 4 * k + 2] = dev[4 + 2 * L + k];
-        h_model_out[4 + 4 * k + 3] = dev[4 + 3 * L + k];
+        h_model_out[4 + 4 * k + 0] = dev[4 + 4 * k + 0];   // device leaf: {X, y, s, yhi}
+        h_model_out[4 + 4 * k + 1] = dev[4 + 4 * k + 1];
+        h_model_out[4 + 4 * k + 2] = dev[4 + 4 * k + 3];
+        h_model_out[4 + 4 * k + 3] = dev[4 + 4 * k + 2];
     }
     return LS_OK;
 }
@@ -750,10 +750,10 @@ ls_status ls_stage_hist(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n,
     uint32_t last = kNoPrev;
     for (uint32_t k = 0; k < leaves; ++k) {
         double X = h_model[4 + 4 * k];
-        dev[4 + k] = X;
-        dev[4 + leaves + k] = h_model[4 + 4 * k + 1];
-        dev[4 + 2 * leaves + k] = h_model[4 + 4 * k + 2];
-        dev[4 + 3 * leaves + k] = h_model[4 + 4 * k + 3];
+        dev[4 + 4 * k + 0] = X;                           // export leaf: {X, y, yhi, s}
+        dev[4 + 4 * k + 1] = h_model[4 + 4 * k + 1];
+        dev[4 + 4 * k + 3] = h_model[4 + 4 * k + 2];
+        dev[4 + 4 * k + 2] = h_model[4 + 4 * k + 3];
         prev[k] = last;
         if (!std::isinf(X))
             last = k;

@@ -1,0 +1,260 @@
+// Device-side building blocks of the LearnedSort 2.0 kernels (gfx950, wave64):
+// key words, the sampler, the model, block scans.
+//
+// Floating point: the model is evaluated in FP64 exactly as written (the
+// library is compiled with -ffp-contract=off; the single fused multiply-add
+// is explicit), so predictions are bit-identical to any IEEE-754 FP64
+// evaluation of the same formulas.
+#pragma once
+#include "lsort_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace lsort {
+
+constexpr uint64_t kSign = 0x8000000000000000ull;
+constexpr uint64_t kSkipBit = 0x8000000000000000ull;
+constexpr uint32_t kNoScatter = 1u;
+constexpr uint32_t kFlagNonMonotone = 0x4u;   // LS_FLAG_NONMONOTONE
+
+// ------------------------------------------------------------------ keys --
+
+// IEEE-754 totalOrder as an unsigned word: negative keys are bit-inverted,
+// non-negative keys get the sign bit set.
+__device__ __forceinline__ uint64_t to_ord(uint64_t raw, uint32_t dt)
+{
+    if (dt != kF64)
+        return raw;
+    return (raw & kSign) ? ~raw : (raw | kSign);
+}
+
+__device__ __forceinline__ uint64_t from_ord(uint64_t o, uint32_t dt)
+{
+    if (dt != kF64)
+        return o;
+    return (o & kSign) ? (o & ~kSign) : ~o;
+}
+
+// Value seen by the model: the double itself, or the u64 rounded to nearest.
+__device__ __forceinline__ double key_value(uint64_t raw, uint32_t dt)
+{
+    return dt == kF64 ? __longlong_as_double((long long)raw) : (double)raw;
+}
+
+__device__ __forceinline__ bool nonfinite(uint64_t raw, uint32_t dt)
+{
+    return dt == kF64 && ((raw >> 52) & 0x7ffu) == 0x7ffu;
+}
+
+__device__ __forceinline__ double ord_value(uint64_t o, uint32_t dt)
+{
+    return key_value(from_ord(o, dt), dt);
+}
+
+// ---------------------------------------------------------------- sampler --
+
+// SplitMix64 (Steele, Lea, Flood 2014): output t of the stream whose state
+// starts at `seed` is the state after t+1 golden-gamma increments, mixed.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t t)
+{
+    uint64_t z = seed + (t + 1u) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t sample_index(uint64_t seed, uint64_t t, uint64_t n)
+{
+    return __umul64hi(splitmix64_at(seed, t), n);
+}
+
+// ------------------------------------------------------------------ model --
+
+// Device model layout at offset o of the pool (doubles):
+//   [xmin, xmax, rs, m'], then per leaf k the segment starting at its knot
+//   {X_k, y_k, s_k, yhi_k} (an empty leaf has X_k = +inf), then L uint32
+//   "previous knot" indices (kNoPrev: none).
+// In LDS the segments are double2 pairs {X, y}, {s, yhi}; entry L is a
+// constant-zero segment that stands for "below the first knot".
+struct SModel {
+    double xmin, rs, lm1;
+    uint32_t L;
+    const double2* seg;     // 2 * (L + 1) entries
+    const uint16_t* prev;   // L entries, L for none
+};
+
+// Copy a model into LDS (all threads participate; caller syncs).
+__device__ __forceinline__ void load_model(SModel& M, const double* pool, uint64_t off, uint32_t L, void* lds)
+{
+    const double* g = pool + off;
+    double2* seg = reinterpret_cast<double2*>(lds);
+    uint16_t* prev = reinterpret_cast<uint16_t*>(seg + 2 * (L + 1));
+    const double2* gs = reinterpret_cast<const double2*>(g + 4);
+    for (uint32_t i = threadIdx.x; i < 2 * L; i += blockDim.x)
+        seg[i] = gs[i];
+    if (threadIdx.x == 0) {
+        seg[2 * L] = make_double2(0.0, 0.0);       // {X, y}: F = y = 0
+        seg[2 * L + 1] = make_double2(0.0, 0.0);   // {s, yhi}: s = 0
+    }
+    const uint32_t* gp = reinterpret_cast<const uint32_t*>(g + 4 + 4 * (size_t)L);
+    for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
+        const uint32_t p = gp[i];
+        prev[i] = (uint16_t)(p == kNoPrev ? L : p);
+    }
+    M.xmin = g[0];
+    M.rs = g[2];
+    M.L = L;
+    M.lm1 = (double)(L - 1u);
+    M.seg = seg;
+    M.prev = prev;
+}
+
+// F(x): fraction of the sample below x, interpolated linearly along the
+// segment of the largest knot not above x (knots: leaf minima of the
+// sample); 0 below the first knot; non-finite keys map to 0 or 1 by sign.
+template <uint32_t DT>
+__device__ __forceinline__ double model_F(const SModel& M, uint64_t raw)
+{
+    const double x = key_value(raw, DT);
+    const double t = (x - M.xmin) * M.rs;
+    const uint32_t k = t >= 1.0 ? (t >= M.lm1 ? M.L - 1u : (uint32_t)t) : 0u;
+    double2 a = M.seg[2 * k];         // {X, y}
+    double2 b = M.seg[2 * k + 1];     // {s, yhi}
+    if (x < a.x) {                    // below this leaf's knot: previous knot
+        const uint32_t j = M.prev[k];
+        a = M.seg[2 * j];
+        b = M.seg[2 * j + 1];
+    }
+    double F = __fma_rn(x - a.x, b.x, a.y);
+    F = F < a.y ? a.y : F;
+    F = F > b.y ? b.y : F;
+    F = b.x == 0.0 ? a.y : F;
+    if (DT == kF64 && nonfinite(raw, kF64))
+        F = (raw & kSign) ? 0.0 : 1.0;
+    return F;
+}
+
+// Bucket of a model task: clamp(floor(F * scale) - offset, 0, fanout - 1);
+// F * scale <= fanout^2 < 2^31, so 32-bit integers are exact.
+template <uint32_t DT>
+__device__ __forceinline__ uint32_t model_bucket(const SModel& M, uint64_t raw, double scale, int32_t offset,
+                                                 uint32_t fanout, uint32_t flags)
+{
+    const double v = model_F<DT>(M, raw) * scale;
+    int32_t q = (int32_t)v - offset;
+    q = q < 0 ? 0 : q;
+    q = q > (int32_t)fanout - 1 ? (int32_t)fanout - 1 : q;
+    uint32_t b = (uint32_t)q;
+    if (flags & kFlagNonMonotone)        // test hook: break monotonicity on purpose
+        b = (raw & 1u) ? (b + fanout / 2u) % fanout : b;
+    return b;
+}
+
+template <uint32_t DT>
+__device__ __forceinline__ uint32_t msd_bucket(uint64_t raw, uint32_t shift, uint32_t fanout)
+{
+    return (uint32_t)((to_ord(raw, DT) >> shift) & (uint64_t)(fanout - 1u));
+}
+
+// ------------------------------------------------------------ block scans --
+
+// Exclusive scan of a[0..n) (LDS, u32) in place; returns the total.
+// wsum: LDS scratch of blockDim/64 + 1 entries.
+__device__ inline uint32_t block_scan_u32(uint32_t* a, uint32_t n, uint32_t* wsum)
+{
+    const uint32_t nt = blockDim.x;
+    const uint32_t per = (n + nt - 1) / nt;
+    const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < hi; ++i)
+        s += a[i];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    uint32_t x = s;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d)
+            x += y;
+    }
+    if (lane == 63)
+        wsum[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t w = 0; w < nt / 64; ++w) {
+            uint32_t v = wsum[w];
+            wsum[w] = run;
+            run += v;
+        }
+        wsum[nt / 64] = run;
+    }
+    __syncthreads();
+    uint32_t base = wsum[wave] + x - s;
+    for (uint32_t i = lo; i < hi; ++i) {
+        uint32_t v = a[i];
+        a[i] = base;
+        base += v;
+    }
+    uint32_t total = wsum[nt / 64];
+    __syncthreads();
+    return total;
+}
+
+// Generic exclusive block scan (LDS, in place) with an associative operator;
+// returns the reduction of all n entries.  wsum: blockDim/64 + 1 entries.
+template <typename T, typename Op>
+__device__ T block_scan_op(T* a, uint32_t n, T ident, Op op, T* wsum)
+{
+    const uint32_t nt = blockDim.x;
+    const uint32_t per = (n + nt - 1) / nt;
+    const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
+    T s = ident;
+    for (uint32_t i = lo; i < hi; ++i)
+        s = op(s, a[i]);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    T x = s;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        T y = __shfl_up(x, d, 64);
+        if (lane >= d)
+            x = op(y, x);
+    }
+    // exclusive prefix within the wave
+    T ex = __shfl_up(x, 1, 64);
+    if (lane == 0)
+        ex = ident;
+    if (lane == 63)
+        wsum[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = ident;
+        for (uint32_t w = 0; w < nt / 64; ++w) {
+            T v = wsum[w];
+            wsum[w] = run;
+            run = op(run, v);
+        }
+        wsum[nt / 64] = run;
+    }
+    __syncthreads();
+    T base = op(wsum[wave], ex);
+    for (uint32_t i = lo; i < hi; ++i) {
+        T v = a[i];
+        a[i] = base;
+        base = op(base, v);
+    }
+    T total = wsum[nt / 64];
+    __syncthreads();
+    return total;
+}
+
+struct MaxI32 {
+    __device__ int32_t operator()(int32_t a, int32_t b) const { return a > b ? a : b; }
+};
+struct MinI32 {
+    __device__ int32_t operator()(int32_t a, int32_t b) const { return a < b ? a : b; }
+};
+struct AddU64 {
+    __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a + b; }
+};
+
+}  // namespace lsort

@@ -96,6 +96,9 @@ struct RoundCtl {
 
 inline size_t model_doubles(uint32_t L) { return 4 + 4 * (size_t)L + (L + 1) / 2; }
 
+// LDS bytes of a model in a partition kernel: L + 1 segments and L indices.
+__host__ __device__ inline size_t model_lds_bytes(uint32_t L) { return (size_t)(L + 1) * 32 + (size_t)L * 2 + 32; }
+
 // Kernel launchers (lsort_kernels.hip).
 hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks,
                         uint64_t* d_sample, uint64_t* d_minmax, uint32_t* d_lcnt, uint64_t* d_lmin,

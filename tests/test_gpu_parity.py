@@ -144,7 +144,7 @@ def test_sort_matches_oracle(S, name, n):
 @pytest.mark.parametrize("kw", [dict(fanout=2), dict(fanout=16, leaves=8), dict(fanout=1000, leaves=1000),
                                 dict(fanout=4096, leaves=256, tile=4096), dict(tile=1024),
                                 dict(base_threshold=2), dict(base_threshold=64, fanout=8),
-                                dict(base_threshold=8192), dict(sample_rate=0.5),
+                                dict(base_threshold=4096, fanout=64), dict(sample_rate=0.5),
                                 dict(sample_cap=100), dict(leaves=1)])
 @pytest.mark.parametrize("name", ["uniform", "zipf", "mixed_u64", "specials", "twovalues"])
 def test_parameters_never_change_the_result(S, kw, name):
