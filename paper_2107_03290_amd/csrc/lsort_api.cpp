@@ -1,10 +1,11 @@
 // Host side of the LearnedSort 2.0 pipeline and the C ABI (include/lsort.h).
 //
 // One sort (or one batch of arrays) runs as:
-//   train   global models on a sample of each large array (Sec. 5.1),
-//   rounds  histogram -> scan -> classify -> scatter over every task of the
-//           round (Alg. 1 as a count-then-place partition), the host reading
-//           back only the next round's task list,
+//   train   global models on a 1% sample of each large array (Sec. 5.1),
+//   rounds  histogram -> scan -> classify -> layout -> scatter over every
+//           task of the round (Alg. 1 as a count-then-place partition; the
+//           next round's task list is built and laid out on the device, the
+//           host reads back one control block per round),
 //   finish  LDS base case over the groups of small buckets, fills of the
 //           all-equal buckets, touch-up seam check (Alg. 2).
 #include "lsort.h"
@@ -15,21 +16,25 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 using namespace lsort;
 
 namespace {
 
-constexpr uint32_t kTargetChunks = 2048;
-constexpr uint32_t kDefaultFanout = 1024;
+constexpr uint32_t kDefaultFanout = 2048;
 constexpr uint32_t kDefaultLeaves = 1024;
-constexpr uint32_t kDefaultTile = 2048;
+constexpr uint32_t kDefaultTile = 4096;
 constexpr uint32_t kDefaultBase = 4096;
 constexpr uint64_t kDefaultSeed = 0x2107032900000001ull;
-constexpr uint32_t kLocalMinSample = 1024;
 
 struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct PinBuf {
     void* p = nullptr;
     size_t cap = 0;
 };
@@ -47,14 +52,6 @@ struct Array {
     uint32_t dtype;
 };
 
-uint64_t mix_host(uint64_t z)
-{
-    // Stafford's Mix13 finaliser: decorrelates local-model seeds.
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
 uint64_t sample_size(uint64_t n, double rate, uint64_t cap)
 {
     double want = std::ceil(rate * (double)n);
@@ -64,14 +61,22 @@ uint64_t sample_size(uint64_t n, double rate, uint64_t cap)
     return m;
 }
 
+uint32_t group_class(uint32_t n)
+{
+    return n <= kGroupClassCap[0] ? 0u : (n <= kGroupClassCap[1] ? 1u : 2u);
+}
+
 }  // namespace
 
 struct ls_ctx {
     int device = 0;
     std::string err;
-    DevBuf scratch, models, sample, minmax, lcnt, lmin, jobs, tasks, next, cnt, pos, scantmp, bstat, skip,
-        tflags, groups, fills, ctl;
-    RoundCtl* h_ctl = nullptr;       // pinned readback
+    DevBuf scratch, models, sample, minmax, lcnt, lmin, gjobs, ljobs, tasks, next, cnt, pos, scantmp, bstat,
+        skip, tflags, fills, ctl;
+    DevBuf groups[kGroupClasses];
+    PinBuf pin_tasks, pin_jobs, pin_groups[kGroupClasses];
+    RoundCtl* h_ctl = nullptr;       // pinned, device-mapped: kernels publish the control block here
+    RoundCtl* d_h_ctl = nullptr;     // its device address
     RoundCtl* h_ctl_init = nullptr;  // pinned upload
     uint64_t stats[8] = {0};
     uint32_t dev_status = 0;
@@ -98,6 +103,13 @@ ls_status fail(ls_ctx* C, ls_status s, const std::string& msg)
             return fail((C), LS_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_));     \
     } while (0)
 
+#define TRY(expr)                       \
+    do {                                \
+        ls_status s_ = (expr);          \
+        if (s_ != LS_OK)                \
+            return s_;                  \
+    } while (0)
+
 // Grow a device buffer; queued work may still use the old one, so wait first.
 ls_status ensure(ls_ctx* C, DevBuf& b, size_t bytes, hipStream_t st, size_t keep = 0)
 {
@@ -117,6 +129,37 @@ ls_status ensure(ls_ctx* C, DevBuf& b, size_t bytes, hipStream_t st, size_t keep
         HIPCHECK(C, hipFree(b.p));
     b.p = np;
     b.cap = nb;
+    return LS_OK;
+}
+
+// Pinned staging for asynchronous uploads.
+ls_status ensure_pinned(ls_ctx* C, PinBuf& b, size_t bytes, hipStream_t st)
+{
+    if (bytes <= b.cap && b.p)
+        return LS_OK;
+    HIPCHECK(C, hipStreamSynchronize(st));
+    if (b.p)
+        HIPCHECK(C, hipHostFree(b.p));
+    b.p = nullptr;
+    size_t nb = std::max<size_t>({bytes, b.cap * 2, 4096});
+    if (hipHostMalloc(&b.p, nb, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        b.cap = 0;
+        return fail(C, LS_ERR_NOMEM, "pinned host allocation failed");
+    }
+    b.cap = nb;
+    return LS_OK;
+}
+
+template <typename T>
+ls_status upload(ls_ctx* C, PinBuf& pin, DevBuf& dst, const std::vector<T>& v, hipStream_t st)
+{
+    if (v.empty())
+        return LS_OK;
+    const size_t bytes = v.size() * sizeof(T);
+    TRY(ensure_pinned(C, pin, bytes, st));
+    std::memcpy(pin.p, v.data(), bytes);
+    HIPCHECK(C, hipMemcpyAsync(dst.p, pin.p, bytes, hipMemcpyHostToDevice, st));
     return LS_OK;
 }
 
@@ -172,13 +215,6 @@ struct Prof {
     }
 };
 
-#define TRY(expr)                       \
-    do {                                \
-        ls_status s_ = (expr);          \
-        if (s_ != LS_OK)                \
-            return s_;                  \
-    } while (0)
-
 ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
 {
     P.fanout = kDefaultFanout;
@@ -211,20 +247,21 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
         return fail(C, LS_ERR_INVALID, "base_threshold must be in [2, 4096]");
     if (!(P.rate > 0.0) || P.rate > 1.0)
         return fail(C, LS_ERR_INVALID, "sample_rate must be in (0, 1]");
-    size_t scatter_lds = (((size_t)P.tile * 10 + (size_t)P.fanout * 16 + 15) & ~(size_t)15) + model_lds_bytes(P.leaves) + 128;
+    size_t scatter_lds = (((size_t)P.tile * 10 + (size_t)P.fanout * 16 + 15) & ~(size_t)15) +
+                         model_lds_bytes(P.leaves) + 128;
     size_t hist_lds = (((size_t)P.fanout * 20 + 15) & ~(size_t)15) + model_lds_bytes(P.leaves) + 64;
     if (scatter_lds > C->lds_limit || hist_lds > C->lds_limit)
         return fail(C, LS_ERR_UNSUPPORTED, "tile/fanout/leaves exceed the LDS of one workgroup");
     return LS_OK;
 }
 
+// Global models of the large arrays, built on the host.
 struct Trainer {
     std::vector<ModelJob> jobs;
     uint64_t samples = 0, leaves = 0, models = 0;
     uint32_t blocks = 0;
 
-    uint64_t add(const uint64_t* src, uint64_t n, uint64_t m, uint64_t seed, uint32_t L, uint32_t dtype,
-                 uint64_t model_base)
+    uint64_t add(const uint64_t* src, uint64_t n, uint64_t m, uint64_t seed, uint32_t L, uint32_t dtype)
     {
         ModelJob J;
         J.src = src;
@@ -232,7 +269,7 @@ struct Trainer {
         J.m = m;
         J.seed = seed;
         J.sample_off = samples;
-        J.model_off = model_base + models;
+        J.model_off = models;
         J.leaf_off = leaves;
         J.leaves = L;
         J.dtype = dtype;
@@ -247,35 +284,51 @@ struct Trainer {
     }
 };
 
-ls_status run_training(ls_ctx* C, Trainer& T, uint64_t model_base, hipStream_t st, Prof* prof = nullptr)
+// Train njobs models described by d_jobs (device) into the pool at model_base.
+ls_status train(ls_ctx* C, const DevBuf& jobs, uint32_t njobs, uint32_t blocks, uint64_t samples, uint64_t leafs,
+                uint64_t model_base, uint64_t models, hipStream_t st, Prof* prof)
 {
-    if (T.jobs.empty())
+    if (!njobs)
         return LS_OK;
-    TRY(ensure(C, C->models, (model_base + T.models) * sizeof(double), st, model_base * sizeof(double)));
-    TRY(ensure(C, C->sample, T.samples * 8, st));
-    TRY(ensure(C, C->minmax, T.jobs.size() * 16, st));
-    TRY(ensure(C, C->lcnt, T.leaves * 4, st));
-    TRY(ensure(C, C->lmin, T.leaves * 8, st));
-    TRY(ensure(C, C->jobs, T.jobs.size() * sizeof(ModelJob), st));
-    HIPCHECK(C, hipMemcpyAsync(C->jobs.p, T.jobs.data(), T.jobs.size() * sizeof(ModelJob), hipMemcpyHostToDevice, st));
+    TRY(ensure(C, C->models, (model_base + models) * sizeof(double), st, model_base * sizeof(double)));
+    TRY(ensure(C, C->sample, samples * 8, st));
+    // the statistics tables start neutral (zero) and the fit kernel leaves
+    // them neutral; only freshly allocated memory needs clearing
+    DevBuf* tabs[3] = {&C->minmax, &C->lcnt, &C->lmin};
+    const size_t need[3] = {(size_t)njobs * 16, leafs * 4, leafs * 8};
+    for (int i = 0; i < 3; ++i) {
+        const void* before = tabs[i]->p;
+        TRY(ensure(C, *tabs[i], need[i], st));
+        if (tabs[i]->p != before)
+            HIPCHECK(C, hipMemsetAsync(tabs[i]->p, 0, tabs[i]->cap, st));
+    }
     if (prof)
         prof->begin(0);
-    HIPCHECK(C, launch_train((const ModelJob*)C->jobs.p, (uint32_t)T.jobs.size(), T.blocks, (uint64_t*)C->sample.p,
-                             (uint64_t*)C->minmax.p, (uint32_t*)C->lcnt.p, (uint64_t*)C->lmin.p,
-                             (double*)C->models.p, st));
+    HIPCHECK(C, launch_train((const ModelJob*)jobs.p, njobs, blocks, (uint64_t*)C->sample.p, (uint64_t*)C->minmax.p,
+                             (uint32_t*)C->lcnt.p, (uint64_t*)C->lmin.p, (double*)C->models.p, st));
     if (prof)
-        prof->end((double)T.samples * 16.0);
-    // the job table is reused by the next training call: keep it alive
+        prof->end((double)samples * 16.0);
+    return LS_OK;
+}
+
+ls_status read_ctl(ls_ctx* C, hipStream_t st)
+{
+    HIPCHECK(C, hipMemcpyAsync(C->h_ctl, C->ctl.p, sizeof(RoundCtl), hipMemcpyDeviceToHost, st));
     HIPCHECK(C, hipStreamSynchronize(st));
-    if (prof)
-        prof->collect();
+    return LS_OK;
+}
+
+// The layout (alone, or at the end of classify) already wrote the control
+// block into mapped host memory: only wait for the stream.
+ls_status wait_ctl(ls_ctx* C, hipStream_t st)
+{
+    HIPCHECK(C, hipStreamSynchronize(st));
     return LS_OK;
 }
 
 // The whole pipeline for a batch of arrays.  msd_only: partition on the
 // order-preserving bits alone (the touch-up repair path).
-ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, bool msd_only,
-                       bool* repaired)
+ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, bool msd_only)
 {
     uint64_t total = 0;
     for (auto& a : arrays)
@@ -289,171 +342,158 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         }
     }
     TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
-    std::vector<Group> groups0;
+
+    // Round-0 work: small arrays go straight to the base case, large ones
+    // get a global model (level 0 of Alg. 2).
+    std::vector<Group> groups0[kGroupClasses];
     std::vector<Task> tasks;
     Trainer tr;
-    uint32_t lf = 31u - (uint32_t)__builtin_clz(P.fanout);
+    const uint32_t lf = 31u - (uint32_t)__builtin_clz(P.fanout);
+    uint64_t group0_keys = 0;
     for (uint32_t i = 0; i < arrays.size(); ++i) {
         const Array& a = arrays[i];
         if (a.n <= 1)
             continue;
         if (a.n <= 2ull * P.base) {
-            groups0.push_back(Group{a.keys, a.keys, 0, (uint32_t)a.n, a.dtype});
+            groups0[group_class((uint32_t)a.n)].push_back(Group{a.keys, a.keys, 0, (uint32_t)a.n, a.dtype});
+            group0_keys += a.n;
             continue;
         }
         Task t{};
         t.keys = a.keys;
         t.scratch = a.scratch;
-        t.start = 0;
         t.n = a.n;
         t.dtype = a.dtype;
-        t.src = 0;
-        t.level = 0;
         t.seg = i;
         if (msd_only) {
             t.kind = kMsd;
             t.fanout = 1u << lf;
             t.shift = 64 - lf;
         } else {
-            uint64_t m = sample_size(a.n, P.rate, P.cap);
             t.kind = kGlobal;
             t.fanout = P.fanout;
             t.scale = (double)P.fanout;
-            t.offset = 0;
             t.leaves = P.leaves;
-            t.model = tr.add(a.keys, a.n, m, P.seed, P.leaves, a.dtype, 0);
+            t.model = tr.add(a.keys, a.n, sample_size(a.n, P.rate, P.cap), P.seed, P.leaves, a.dtype);
         }
         tasks.push_back(t);
     }
     const uint64_t global_models = tr.models;
     Prof prof{C, st, (P.flags & LS_FLAG_PROFILE) != 0, {}};
-    TRY(run_training(C, tr, 0, st, &prof));
 
-    // cumulative lists
-    uint64_t ngroups = groups0.size(), nfill = 0;
-    uint64_t group0_keys = 0;
-    for (auto& g : groups0)
-        group0_keys += g.n;
-    std::memset(C->h_ctl, 0, sizeof(RoundCtl));
-    TRY(ensure(C, C->groups, std::max<uint64_t>(ngroups, 1) * sizeof(Group), st));
-    if (ngroups)
-        HIPCHECK(C, hipMemcpyAsync(C->groups.p, groups0.data(), ngroups * sizeof(Group), hipMemcpyHostToDevice, st));
     std::memset(C->h_ctl_init, 0, sizeof(RoundCtl));
-    C->h_ctl_init->ngroups = (uint32_t)ngroups;
+    C->h_ctl_init->ntasks = (uint32_t)tasks.size();
+    for (uint32_t c = 0; c < kGroupClasses; ++c) {
+        C->h_ctl_init->ngroups[c] = (uint32_t)groups0[c].size();
+        TRY(ensure(C, C->groups[c], std::max<size_t>(groups0[c].size(), 1) * sizeof(Group), st));
+        TRY(upload(C, C->pin_groups[c], C->groups[c], groups0[c], st));
+    }
     HIPCHECK(C, hipMemcpyAsync(C->ctl.p, C->h_ctl_init, sizeof(RoundCtl), hipMemcpyHostToDevice, st));
-    HIPCHECK(C, hipStreamSynchronize(st));   // h_ctl_init is reused below
+    TRY(ensure(C, C->next, std::max<size_t>(tasks.size(), 1) * sizeof(Task), st));
+    TRY(ensure(C, C->ljobs, std::max<size_t>(tasks.size(), 1) * sizeof(ModelJob), st));
+    TRY(upload(C, C->pin_tasks, C->next, tasks, st));
+    if (!tr.jobs.empty()) {
+        TRY(ensure(C, C->gjobs, tr.jobs.size() * sizeof(ModelJob), st));
+        TRY(upload(C, C->pin_jobs, C->gjobs, tr.jobs, st));
+        TRY(train(C, C->gjobs, (uint32_t)tr.jobs.size(), tr.blocks, tr.samples, tr.leaves, 0, tr.models, st, &prof));
+    }
+    LayoutParams lp;
+    lp.fanout = P.fanout;
+    lp.leaves = P.leaves;
+    lp.tile = P.tile;
+    lp.pad = 0;
+    lp.rate = P.rate;
+    lp.cap = P.cap;
+    lp.seed = P.seed;
+    lp.model_base = global_models;
+    if (!tasks.empty()) {
+        HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp, (RoundCtl*)C->ctl.p, C->d_h_ctl,
+                                  st));
+        TRY(wait_ctl(C, st));
+    } else {
+        TRY(read_ctl(C, st));
+    }
+    prof.collect();
 
     uint64_t rounds = 0, ntasks_total = 0;
     uint32_t max_level = 0;
     const uint32_t flags = msd_only ? 0u : (P.flags & LS_FLAG_NONMONOTONE);
-    while (!tasks.empty()) {
+    while (C->h_ctl->ntasks) {
+        const RoundCtl R = *C->h_ctl;
+        const uint32_t nt = R.ntasks;
         ++rounds;
-        ntasks_total += tasks.size();
-        // layout of the round: chunks, bucket table, count matrix
-        uint64_t Nr = 0;
-        for (auto& t : tasks)
-            Nr += t.n;
-        uint64_t chunk = (Nr + kTargetChunks - 1) / kTargetChunks;
-        chunk = std::max<uint64_t>(P.tile * 4ull, (chunk + P.tile - 1) / P.tile * P.tile);
-        uint64_t E = 0, base = 0;
-        uint32_t chunks = 0, buckets = 0, max_f = 2, max_L = 1;
-        for (auto& t : tasks) {
-            t.nchunks = (uint32_t)((t.n + chunk - 1) / chunk);
-            t.chunk0 = chunks;
-            t.bucket_off = buckets;
-            t.cnt_off = E;
-            t.cnt_base = base;
-            chunks += t.nchunks;
-            buckets += t.fanout;
-            E += (uint64_t)t.fanout * t.nchunks;
-            base += t.n;
-            max_f = std::max(max_f, t.fanout);
-            if (t.kind != kMsd)
-                max_L = std::max(max_L, t.leaves);
-            max_level = std::max(max_level, t.level);
+        ntasks_total += nt;
+        max_level = std::max(max_level, R.max_level);
+        std::swap(C->tasks, C->next);
+        TRY(ensure(C, C->cnt, R.entries * 4, st));
+        TRY(ensure(C, C->pos, R.entries * 8, st));
+        TRY(ensure(C, C->scantmp, scan_tmp_entries(R.entries) * 8, st));
+        TRY(ensure(C, C->bstat, (uint64_t)R.buckets * 16, st));
+        TRY(ensure(C, C->skip, R.buckets, st));
+        TRY(ensure(C, C->tflags, (size_t)nt * 4, st));
+        TRY(ensure(C, C->next, (size_t)R.buckets * sizeof(Task), st));
+        GroupLists gl;
+        for (uint32_t c = 0; c < kGroupClasses; ++c) {
+            TRY(ensure(C, C->groups[c], ((size_t)R.ngroups[c] + R.buckets) * sizeof(Group), st,
+                       (size_t)R.ngroups[c] * sizeof(Group)));
+            gl.g[c] = (Group*)C->groups[c].p;
         }
-        const uint32_t nt = (uint32_t)tasks.size();
-        TRY(ensure(C, C->tasks, nt * sizeof(Task), st));
-        TRY(ensure(C, C->cnt, E * 4, st));
-        TRY(ensure(C, C->pos, E * 8, st));
-        TRY(ensure(C, C->scantmp, scan_tmp_entries(E) * 8, st));
-        TRY(ensure(C, C->bstat, (uint64_t)buckets * 16, st));
-        TRY(ensure(C, C->skip, buckets, st));
-        TRY(ensure(C, C->tflags, nt * 4, st));
-        TRY(ensure(C, C->next, (uint64_t)buckets * sizeof(Task), st));
-        TRY(ensure(C, C->groups, (ngroups + buckets) * sizeof(Group), st, ngroups * sizeof(Group)));
-        TRY(ensure(C, C->fills, (nfill + buckets + Nr / kFillPiece + 1) * sizeof(Fill), st, nfill * sizeof(Fill)));
-        HIPCHECK(C, hipMemcpyAsync(C->tasks.p, tasks.data(), nt * sizeof(Task), hipMemcpyHostToDevice, st));
-        HIPCHECK(C, hipMemsetAsync(C->ctl.p, 0, sizeof(uint32_t), st));   // ntasks = 0
-        const RoundCtl before = *C->h_ctl;
-        HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, buckets, st));
+        TRY(ensure(C, C->fills, ((size_t)R.nfill + R.buckets + R.nkeys / kFillPiece + 1) * sizeof(Fill), st,
+                   (size_t)R.nfill * sizeof(Fill)));
+        // local models of this round's tasks (jobs written by the last layout)
+        TRY(train(C, C->ljobs, R.njobs, R.blocks, R.samples, R.leafs, global_models, R.models, st, &prof));
+        TRY(ensure(C, C->ljobs, (size_t)R.buckets * sizeof(ModelJob), st));
+        HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, R.buckets, (RoundCtl*)C->ctl.p, st));
         prof.begin(1);
-        HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, chunks, chunk, (const double*)C->models.p,
-                                (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, max_f, max_L, flags, st));
-        prof.end((double)Nr * 8.0);
+        HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
+                                (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, R.max_fanout, R.max_leaves, flags, st));
+        prof.end((double)R.nkeys * 8.0);
         prof.begin(2);
-        HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, E, (uint64_t*)C->scantmp.p, st));
-        prof.end((double)E * 16.0);
+        HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, R.entries, (uint64_t*)C->scantmp.p,
+                                st));
+        prof.end((double)R.entries * 16.0);
         prof.begin(3);
         HIPCHECK(C, launch_classify((const Task*)C->tasks.p, nt, (const uint64_t*)C->pos.p,
-                                    (const uint64_t*)C->bstat.p, P.base, P.fanout, (Task*)C->next.p,
-                                    (Group*)C->groups.p, (Fill*)C->fills.p, (uint8_t*)C->skip.p,
-                                    (uint32_t*)C->tflags.p, (RoundCtl*)C->ctl.p, max_f, st));
-        prof.end((double)buckets * 32.0);
+                                    (const uint64_t*)C->bstat.p, P.base, P.fanout, (Task*)C->next.p, gl,
+                                    (Fill*)C->fills.p, (uint8_t*)C->skip.p, (uint32_t*)C->tflags.p,
+                                    (RoundCtl*)C->ctl.p, R.max_fanout, (ModelJob*)C->ljobs.p, lp, C->d_h_ctl,
+                                    st));
+        prof.end((double)R.buckets * 32.0);
         prof.begin(4);
-        HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, chunks, chunk, (const double*)C->models.p,
+        HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
                                    (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
-                                   (const uint32_t*)C->tflags.p, P.tile, max_f, max_L, flags, st));
+                                   (const uint32_t*)C->tflags.p, P.tile, R.max_fanout, R.max_leaves, flags, st));
         prof.end(0.0);
-        HIPCHECK(C, hipMemcpyAsync(C->h_ctl, C->ctl.p, sizeof(RoundCtl), hipMemcpyDeviceToHost, st));
-        HIPCHECK(C, hipStreamSynchronize(st));
+        TRY(wait_ctl(C, st));
         if (prof.on && !prof.recs.empty()) {
             // scatter: reads every key of a task that progressed, writes those not in all-equal buckets
-            const double moved = (double)(Nr - (C->h_ctl->stall_keys - before.stall_keys));
-            const double kept = moved - (double)(C->h_ctl->fillkeys - before.fillkeys);
+            const double moved = (double)(R.nkeys - (C->h_ctl->stall_keys - R.stall_keys));
+            const double kept = moved - (double)(C->h_ctl->fillkeys - R.fillkeys);
             prof.recs.back().bytes = 8.0 * moved + 8.0 * kept;
         }
         prof.collect();
-        const uint32_t nnext = C->h_ctl->ntasks;
-        ngroups = C->h_ctl->ngroups;
-        nfill = C->h_ctl->nfill;
-        tasks.resize(nnext);
-        if (nnext)
-            HIPCHECK(C, hipMemcpy(tasks.data(), C->next.p, nnext * sizeof(Task), hipMemcpyDeviceToHost));
-        // local models for the next round
-        Trainer lt;
-        for (auto& t : tasks) {
-            if (t.kind != kLocal)
-                continue;
-            uint64_t m = std::max<uint64_t>(std::min<uint64_t>(t.n, kLocalMinSample), sample_size(t.n, P.rate, 0));
-            if (P.cap && m > P.cap)
-                m = std::max<uint64_t>(P.cap, std::min<uint64_t>(t.n, kLocalMinSample));
-            uint32_t L = (uint32_t)std::min<uint64_t>(P.leaves, m);
-            uint64_t seed = mix_host(P.seed ^ mix_host(t.start + 0x9e3779b97f4a7c15ull * (t.level + 1)) ^
-                                     ((uint64_t)t.seg << 32));
-            const uint64_t* src = (t.src ? t.scratch : t.keys) + t.start;
-            t.leaves = L;
-            t.model = lt.add(src, t.n, m, seed, L, t.dtype, global_models);
-        }
-        TRY(run_training(C, lt, global_models, st, &prof));
     }
+
     // finish: LDS base case, all-equal fills, touch-up
-    const double gkeys = (double)C->h_ctl->group_keys + (double)group0_keys;
-    const double fkeys = (double)C->h_ctl->fillkeys;
+    const RoundCtl F = *C->h_ctl;
+    GroupLists gl;
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        gl.g[c] = (Group*)C->groups[c].p;
+    const double gkeys = (double)F.group_keys + (double)group0_keys;
     prof.begin(5);
-    HIPCHECK(C, launch_base((const Group*)C->groups.p, (uint32_t)ngroups, 2 * P.base, st));
+    HIPCHECK(C, launch_base(gl, F.ngroups, st));
     prof.end(16.0 * gkeys);
     prof.begin(6);
-    HIPCHECK(C, launch_fill((const Fill*)C->fills.p, (uint32_t)nfill, st));
-    prof.end(8.0 * fkeys);
+    HIPCHECK(C, launch_fill((const Fill*)C->fills.p, F.nfill, st));
+    prof.end(8.0 * (double)F.fillkeys);
     prof.begin(7);
-    HIPCHECK(C, launch_touchup((const Group*)C->groups.p, (uint32_t)ngroups, (const Fill*)C->fills.p,
-                               (uint32_t)nfill, (P.flags & LS_FLAG_DEBUG_TOUCHUP) ? 1 : 0, (RoundCtl*)C->ctl.p, st));
-    prof.end(16.0 * (double)(ngroups + nfill));
-    HIPCHECK(C, hipMemcpyAsync(C->h_ctl, C->ctl.p, sizeof(RoundCtl), hipMemcpyDeviceToHost, st));
-    HIPCHECK(C, hipStreamSynchronize(st));
+    HIPCHECK(C, launch_touchup(gl, F.ngroups, (const Fill*)C->fills.p, F.nfill,
+                               (P.flags & LS_FLAG_DEBUG_TOUCHUP) ? 1 : 0, (RoundCtl*)C->ctl.p, st));
+    const uint64_t ngroups = (uint64_t)F.ngroups[0] + F.ngroups[1] + F.ngroups[2];
+    prof.end(16.0 * (double)(ngroups + F.nfill));
+    TRY(read_ctl(C, st));
     prof.collect();
-    RoundCtl fin = *C->h_ctl;
+    const RoundCtl fin = *C->h_ctl;
     C->stats[0] = rounds;
     C->stats[1] = ntasks_total;
     C->stats[2] = ngroups;
@@ -473,11 +513,9 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         // with the test hook); re-partition on the key bits alone.
         uint64_t saved[8];
         std::memcpy(saved, C->stats, sizeof saved);
-        TRY(run_pipeline(C, arrays, st, P, true, nullptr));
+        TRY(run_pipeline(C, arrays, st, P, true));
         std::memcpy(C->stats, saved, sizeof saved);
         C->dev_status |= LS_DEV_SEAM_REPAIRED;
-        if (repaired)
-            *repaired = true;
     }
     return LS_OK;
 }
@@ -497,7 +535,7 @@ ls_status sort_arrays(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, con
     HIPCHECK(C, hipSetDevice(C->device));
     C->dev_status = 0;
     std::memset(C->stats, 0, sizeof C->stats);
-    return run_pipeline(C, arrays, st, P, false, nullptr);
+    return run_pipeline(C, arrays, st, P, false);
 }
 
 }  // namespace
@@ -535,7 +573,9 @@ ls_status ls_create(ls_ctx** out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess)
         C->lds_limit = prop.sharedMemPerBlock;
-    if (hipHostMalloc((void**)&C->h_ctl, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void**)&C->h_ctl, sizeof(RoundCtl), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void**)&C->d_h_ctl, C->h_ctl, 0) != hipSuccess ||
         hipHostMalloc((void**)&C->h_ctl_init, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess) {
         delete C;
         return LS_ERR_NOMEM;
@@ -550,12 +590,16 @@ ls_status ls_destroy(ls_ctx* C)
         return LS_ERR_INVALID;
     (void)hipSetDevice(C->device);
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&C->scratch, &C->models, &C->sample, &C->minmax, &C->lcnt, &C->lmin, &C->jobs,
-                      &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat, &C->skip,
-                      &C->tflags, &C->groups, &C->fills, &C->ctl};
+    DevBuf* bufs[] = {&C->scratch, &C->models, &C->sample, &C->minmax, &C->lcnt, &C->lmin, &C->gjobs,
+                      &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
+                      &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2]};
     for (DevBuf* b : bufs)
         if (b->p)
             (void)hipFree(b->p);
+    PinBuf* pins[] = {&C->pin_tasks, &C->pin_jobs, &C->pin_groups[0], &C->pin_groups[1], &C->pin_groups[2]};
+    for (PinBuf* b : pins)
+        if (b->p)
+            (void)hipHostFree(b->p);
     if (C->h_ctl)
         (void)hipHostFree(C->h_ctl);
     if (C->h_ctl_init)
@@ -715,9 +759,13 @@ ls_status ls_model_train(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n
     if (cap < 4 + 4 * (size_t)P.leaves)
         return fail(C, LS_ERR_INVALID, "model output buffer too small");
     HIPCHECK(C, hipSetDevice(C->device));
+    hipStream_t st = nullptr;
     Trainer tr;
-    tr.add((const uint64_t*)d_keys, n, sample_size(n, P.rate, P.cap), P.seed, P.leaves, dtype, 0);
-    TRY(run_training(C, tr, 0, nullptr));
+    tr.add((const uint64_t*)d_keys, n, sample_size(n, P.rate, P.cap), P.seed, P.leaves, dtype);
+    TRY(ensure(C, C->gjobs, sizeof(ModelJob), st));
+    TRY(upload(C, C->pin_jobs, C->gjobs, tr.jobs, st));
+    TRY(train(C, C->gjobs, 1, tr.blocks, tr.samples, tr.leaves, 0, tr.models, st, nullptr));
+    HIPCHECK(C, hipStreamSynchronize(st));
     std::vector<double> dev(model_doubles(P.leaves));
     HIPCHECK(C, hipMemcpy(dev.data(), C->models.p, dev.size() * 8, hipMemcpyDeviceToHost));
     const uint32_t L = P.leaves;
@@ -759,31 +807,25 @@ ls_status ls_stage_hist(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n,
             last = k;
     }
     TRY(ensure(C, C->models, dev.size() * 8, st));
+    TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
     HIPCHECK(C, hipMemcpy(C->models.p, dev.data(), dev.size() * 8, hipMemcpyHostToDevice));
     const uint32_t tile = kDefaultTile;
     uint64_t chunk = std::max<uint64_t>(tile * 4ull, ((n + kTargetChunks - 1) / kTargetChunks + tile - 1) / tile * tile);
     Task t{};
     t.keys = (uint64_t*)d_keys;
-    t.scratch = nullptr;
-    t.start = 0;
     t.n = n;
-    t.model = 0;
     t.scale = scale;
     t.offset = offset;
     t.fanout = fanout;
     t.kind = kGlobal;
     t.dtype = dtype;
-    t.src = 0;
     t.leaves = leaves;
     t.nchunks = (uint32_t)((n + chunk - 1) / chunk);
-    t.chunk0 = 0;
-    t.bucket_off = 0;
-    t.cnt_off = 0;
     TRY(ensure(C, C->tasks, sizeof(Task), st));
     TRY(ensure(C, C->cnt, (size_t)fanout * t.nchunks * 4, st));
     TRY(ensure(C, C->bstat, (size_t)fanout * 16, st));
     HIPCHECK(C, hipMemcpy(C->tasks.p, &t, sizeof(Task), hipMemcpyHostToDevice));
-    HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, fanout, st));
+    HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, fanout, (RoundCtl*)C->ctl.p, st));
     HIPCHECK(C, launch_hist((const Task*)C->tasks.p, 1, t.nchunks, chunk, (const double*)C->models.p,
                             (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, fanout, leaves, 0, st));
     HIPCHECK(C, hipDeviceSynchronize());

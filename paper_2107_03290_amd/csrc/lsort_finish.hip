@@ -1,7 +1,6 @@
-// Finishing steps: LDS base case, all-equal fills, touch-up check (Alg. 2).
+// Finishing steps (Alg. 2): LDS base case over groups of small buckets,
+// fills of all-equal buckets, touch-up check of the seams between ranges.
 #include "lsort_device.h"
-
-#pragma clang fp contract(off)
 
 namespace lsort {
 
@@ -12,10 +11,9 @@ namespace lsort {
 // Each thread keeps 16 elements in registers: the 16 indices that differ only
 // in a window of 4 index bits.  Up to four consecutive stages of the network
 // touch only bits inside one window, so each LDS round trip runs four stages
-// in registers; a phase of the network needs ceil(p/4) round trips.
-constexpr uint32_t kBaseThreads = 512;
-constexpr uint32_t kBaseMax = kBaseThreads * 16;
-
+// in registers; a phase of the network needs ceil(p/4) round trips.  Groups
+// come in three size classes so that small groups run in small workgroups:
+// up to 1024 keys on 64 lanes, 4096 on 256, 8192 on 512.
 __host__ __device__ __forceinline__ uint32_t base_pad(uint32_t i) { return i + (i >> 4); }
 
 // element index of register m of thread t, the 4 register bits at [lo, lo+4)
@@ -47,13 +45,14 @@ __device__ __forceinline__ void reg_stages(uint64_t (&r)[16], uint32_t top, bool
     }
 }
 
-__global__ __launch_bounds__(kBaseThreads) void k_base(const Group* groups)
+template <uint32_t NT>
+__global__ __launch_bounds__(NT) void k_base(const Group* groups)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t* s = reinterpret_cast<uint64_t*>(smem);
     const Group G = groups[blockIdx.x];
     const uint32_t n = G.n;
-    if (n > kBaseMax)            // never produced by the grouping rule; keeps LDS in bounds
+    if (n > NT * 16u)            // never produced by classify; keeps LDS in bounds
         return;
     uint32_t logN = 4;
     while ((1u << logN) < n)
@@ -61,7 +60,7 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const Group* groups)
     const uint32_t N = 1u << logN;
     const uint32_t t = threadIdx.x;
     const bool act = t < (N >> 4);
-    for (uint32_t i = t; i < N; i += kBaseThreads)
+    for (uint32_t i = t; i < N; i += NT)
         s[base_pad(i)] = i < n ? to_ord(G.src[i], G.dtype) : ~0ull;
     __syncthreads();
     uint64_t r[16];
@@ -109,19 +108,22 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const Group* groups)
             bit = (int32_t)lo - 1;
         }
     }
-    for (uint32_t i = t; i < n; i += kBaseThreads)
+    for (uint32_t i = t; i < n; i += NT)
         G.dst[i] = from_ord(s[base_pad(i)], G.dtype);
 }
 
-hipError_t launch_base(const Group* d_groups, uint32_t ngroups, uint32_t base_cap, hipStream_t st)
+hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, hipStream_t st)
 {
-    if (!ngroups)
-        return hipSuccess;
-    if (base_cap > kBaseMax)
-        return hipErrorInvalidValue;
-    k_base<<<ngroups, kBaseThreads, (size_t)base_pad(kBaseMax) * 8, st>>>(d_groups);
+    if (ngroups[0])
+        k_base<64><<<ngroups[0], 64, (size_t)base_pad(kGroupClassCap[0]) * 8, st>>>(groups.g[0]);
+    if (ngroups[1])
+        k_base<256><<<ngroups[1], 256, (size_t)base_pad(kGroupClassCap[1]) * 8, st>>>(groups.g[1]);
+    if (ngroups[2])
+        k_base<512><<<ngroups[2], 512, (size_t)base_pad(kGroupClassCap[2]) * 8, st>>>(groups.g[2]);
     return hipGetLastError();
 }
+
+// ------------------------------------------------------------------ fill --
 
 __global__ __launch_bounds__(256) void k_fill(const Fill* fills)
 {
@@ -137,26 +139,39 @@ hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, hipStream_t st)
     return hipGetLastError();
 }
 
+// -------------------------------------------------------------- touch-up --
+
 // Touch-up check (Alg. 2's final pass): every final range is sorted by
 // construction, so only the seam with the preceding range can be out of
 // order.  `full` also rechecks every adjacent pair inside the groups.
-__global__ __launch_bounds__(256) void k_touchup(const Group* groups, uint32_t ngroups, const Fill* fills,
-                                                 uint32_t nfill, RoundCtl* ctl)
+struct RangeLists {
+    const Group* g[kGroupClasses];
+    uint32_t ng[kGroupClasses];
+    const Fill* fills;
+    uint32_t nfill;
+};
+
+__global__ __launch_bounds__(256) void k_touchup(RangeLists R, RoundCtl* ctl)
 {
     uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    const uint64_t* p;
-    uint64_t start;
-    uint32_t dt;
-    if (i < ngroups) {
-        p = groups[i].dst;
-        start = groups[i].start;
-        dt = groups[i].dtype;
-    } else if (i < ngroups + nfill) {
-        p = fills[i - ngroups].dst;
-        start = fills[i - ngroups].start;
-        dt = fills[i - ngroups].dtype;
-    } else {
-        return;
+    const uint64_t* p = nullptr;
+    uint64_t start = 0;
+    uint32_t dt = 0;
+    for (uint32_t c = 0; c < kGroupClasses && !p; ++c) {
+        if (i < R.ng[c]) {
+            p = R.g[c][i].dst;
+            start = R.g[c][i].start;
+            dt = R.g[c][i].dtype;
+        } else {
+            i -= R.ng[c];
+        }
+    }
+    if (!p) {
+        if (i >= R.nfill)
+            return;
+        p = R.fills[i].dst;
+        start = R.fills[i].start;
+        dt = R.fills[i].dtype;
     }
     if (start > 0 && to_ord(p[-1], dt) > to_ord(p[0], dt))
         atomicAdd(&ctl->violations, 1u);
@@ -172,14 +187,24 @@ __global__ __launch_bounds__(256) void k_touchup_full(const Group* groups, Round
         atomicAdd(&ctl->violations, bad);
 }
 
-hipError_t launch_touchup(const Group* d_groups, uint32_t ngroups, const Fill* d_fills, uint32_t nfill, int full,
+hipError_t launch_touchup(GroupLists groups, const uint32_t* ngroups, const Fill* d_fills, uint32_t nfill, int full,
                           RoundCtl* d_ctl, hipStream_t st)
 {
-    uint32_t items = ngroups + nfill;
+    RangeLists R;
+    uint64_t items = nfill;
+    for (uint32_t c = 0; c < kGroupClasses; ++c) {
+        R.g[c] = groups.g[c];
+        R.ng[c] = ngroups[c];
+        items += ngroups[c];
+    }
+    R.fills = d_fills;
+    R.nfill = nfill;
     if (items)
-        k_touchup<<<(items + 255) / 256, 256, 0, st>>>(d_groups, ngroups, d_fills, nfill, d_ctl);
-    if (full && ngroups)
-        k_touchup_full<<<ngroups, 256, 0, st>>>(d_groups, d_ctl);
+        k_touchup<<<(uint32_t)((items + 255) / 256), 256, 0, st>>>(R, d_ctl);
+    if (full)
+        for (uint32_t c = 0; c < kGroupClasses; ++c)
+            if (ngroups[c])
+                k_touchup_full<<<ngroups[c], 256, 0, st>>>(groups.g[c], d_ctl);
     return hipGetLastError();
 }
 

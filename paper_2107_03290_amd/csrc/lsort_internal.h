@@ -14,11 +14,15 @@ constexpr uint32_t kMaxLeaves = 1024;
 constexpr uint32_t kMaxBase = 8192;        // largest group the LDS base case sorts
 constexpr uint32_t kNoPrev = 0xffffu;      // "no knot below": F = 0
 constexpr uint64_t kFillPiece = 1u << 16;  // keys per fill work item
+constexpr uint32_t kTargetChunks = 2048;   // chunks per partition round (8 per CU)
+constexpr uint32_t kLocalMinSample = 1024; // smallest sample of a local model
+constexpr uint32_t kGroupClasses = 3;      // base-case size classes: <= 1024, 4096, 8192 keys
+constexpr uint32_t kGroupClassCap[kGroupClasses] = {1024, 4096, 8192};
 
 // How a task maps a key to a bucket.
 enum TaskKind : uint32_t {
     kGlobal = 0,     // level 0: floor(F * f), F the array's model
-    kGlobalL1 = 1,   // level 1 under parent i: floor(F * f^2) - i*f (same model)
+    kGlobalL1 = 1,   // level 1 under parent i: floor(F * f * f1) - i*f1 (same model)
     kLocal = 2,      // deeper: floor(F_local * f), model trained on the range
     kMsd = 3,        // no model progress: digit of the order-preserving word
 };
@@ -30,8 +34,8 @@ struct Task {
     uint64_t start;       // first key of the range, relative to the array
     uint64_t n;           // keys in the range
     uint64_t model;       // offset (in doubles) of the model in the model pool
-    double scale;         // kGlobal / kLocal: f; kGlobalL1: f*f
-    int64_t offset;       // kGlobalL1: i*f
+    double scale;         // kGlobal / kLocal: f; kGlobalL1: f * f1
+    int64_t offset;       // kGlobalL1: i * f1
     uint32_t fanout;
     uint32_t kind;        // TaskKind
     uint32_t dtype;       // kF64 / kU64
@@ -55,6 +59,11 @@ struct Group {
     uint64_t start;       // of dst, relative to its array (0: no seam to check)
     uint32_t n;
     uint32_t dtype;
+};
+
+// The three size-class lists of groups (device pointers, passed by value).
+struct GroupLists {
+    Group* g[kGroupClasses];
 };
 
 // Part of an all-equal bucket: written with its single value, never sorted.
@@ -81,46 +90,76 @@ struct ModelJob {
     uint32_t nblocks;
 };
 
-// Counters the classify kernel appends to; read by the host after a round.
-struct RoundCtl {
-    uint32_t ntasks;      // next-round tasks
-    uint32_t ngroups;     // base-case groups (cumulative)
-    uint32_t nfill;       // fill items (cumulative)
-    uint32_t nfillbuckets;
-    uint64_t fillkeys;
-    uint32_t fallbacks;
-    uint32_t violations;  // out-of-order seams found by the touch-up
-    uint64_t group_keys;  // keys in base-case groups (cumulative)
-    uint64_t stall_keys;  // keys of tasks that made no progress (not scattered)
+// Parameters the device-side round layout needs.
+struct LayoutParams {
+    uint32_t fanout;      // the caller's fanout
+    uint32_t leaves;
+    uint32_t tile;
+    uint32_t pad;
+    double rate;
+    uint64_t cap;
+    uint64_t seed;
+    uint64_t model_base;  // local models start after the arrays' global models
 };
 
-inline size_t model_doubles(uint32_t L) { return 4 + 4 * (size_t)L + (L + 1) / 2; }
+// Counters the classify and layout kernels fill in; read by the host after
+// each round (one small copy) to size the next round's launches.
+struct RoundCtl {
+    // written by classify (cumulative over rounds unless noted)
+    uint32_t ntasks;                  // next-round tasks (reset every round)
+    uint32_t nfill;                   // fill items
+    uint32_t ngroups[kGroupClasses];  // base-case groups per size class
+    uint32_t nfillbuckets;
+    uint64_t fillkeys;
+    uint64_t group_keys;              // keys in base-case groups
+    uint64_t stall_keys;              // keys of tasks that made no progress (not scattered)
+    uint32_t fallbacks;
+    uint32_t violations;              // out-of-order seams found by the touch-up
+    // written by the layout kernel for the next round
+    uint64_t chunk;                   // keys per chunk
+    uint64_t nkeys;                   // keys in the round's tasks
+    uint64_t entries;                 // count-matrix entries
+    uint64_t samples, leafs, models;  // training-table sizes
+    uint32_t chunks, buckets, njobs, blocks;
+    uint32_t max_fanout, max_leaves, max_level;
+    uint32_t classified;              // classify workgroups finished (reset every round)
+};
+
+__host__ __device__ inline size_t model_doubles(uint32_t L) { return 4 + 4 * (size_t)L + (L + 1) / 2; }
 
 // LDS bytes of a model in a partition kernel: L + 1 segments and L indices.
 __host__ __device__ inline size_t model_lds_bytes(uint32_t L) { return (size_t)(L + 1) * 32 + (size_t)L * 2 + 32; }
 
-// Kernel launchers (lsort_kernels.hip).
+// Kernel launchers.
 hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks,
                         uint64_t* d_sample, uint64_t* d_minmax, uint32_t* d_lcnt, uint64_t* d_lmin,
                         double* d_models, hipStream_t st);
-hipError_t launch_round_init(uint64_t* d_bstat, uint32_t nbuckets, hipStream_t st);
+hipError_t launch_round_init(uint64_t* d_bstat, uint32_t nbuckets, RoundCtl* d_ctl, hipStream_t st);
 hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                        const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint32_t max_fanout,
                        uint32_t max_leaves, uint32_t flags, hipStream_t st);
 hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, hipStream_t st);
 size_t scan_tmp_entries(uint64_t n);
+// Classify every bucket of the round's tasks; the last workgroup to finish
+// then lays out the next round (see launch_layout) and copies the control
+// block to host_ctl (device-visible pinned host memory).
 hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t* d_pos,
-                           const uint64_t* d_bstat, uint32_t base_cap, uint32_t param_fanout,
-                           Task* d_next, Group* d_groups, Fill* d_fills, uint8_t* d_skip,
-                           uint32_t* d_task_flags, RoundCtl* d_ctl, uint32_t max_fanout, hipStream_t st);
+                           const uint64_t* d_bstat, uint32_t thresh, uint32_t param_fanout,
+                           Task* d_next, GroupLists groups, Fill* d_fills, uint8_t* d_skip,
+                           uint32_t* d_task_flags, RoundCtl* d_ctl, uint32_t max_fanout,
+                           ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* host_ctl, hipStream_t st);
+// Lay out the ctl->ntasks tasks of d_next: chunk size and offsets, and a
+// training job for each task that needs a local model; totals go to ctl and
+// to host_ctl.
+hipError_t launch_layout(Task* d_next, ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* d_ctl,
+                         RoundCtl* host_ctl, hipStream_t st);
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                           const double* d_models, const uint64_t* d_pos, const uint8_t* d_skip,
                           const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout,
                           uint32_t max_leaves, uint32_t flags, hipStream_t st);
-hipError_t launch_base(const Group* d_groups, uint32_t ngroups, uint32_t base_cap, hipStream_t st);
+hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, hipStream_t st);
 hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, hipStream_t st);
-hipError_t launch_touchup(const Group* d_groups, uint32_t ngroups, const Fill* d_fills, uint32_t nfill,
+hipError_t launch_touchup(GroupLists groups, const uint32_t* ngroups, const Fill* d_fills, uint32_t nfill,
                           int full, RoundCtl* d_ctl, hipStream_t st);
-
 
 }  // namespace lsort

@@ -1,11 +1,10 @@
-// Partition rounds: histogram, scan, classify, scatter (Alg. 1 / Alg. 2).
+// Partition rounds (Alg. 1 as count-then-place, Alg. 2's recursion):
+// histogram, classify, layout of the next round, scatter.
 #include "lsort_device.h"
 
 #pragma clang fp contract(off)
 
 namespace lsort {
-
-// ------------------------------------------------------- partition rounds --
 
 __device__ __forceinline__ uint32_t find_task(const Task* tasks, uint32_t ntasks, uint32_t chunk)
 {
@@ -17,21 +16,26 @@ __device__ __forceinline__ uint32_t find_task(const Task* tasks, uint32_t ntasks
     return lo;
 }
 
-__global__ void k_round_init(uint64_t* bstat, uint32_t nbuckets)
+__global__ void k_round_init(uint64_t* bstat, uint32_t nbuckets, RoundCtl* ctl)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        ctl->ntasks = 0;
+        ctl->classified = 0;
+    }
     if (i < nbuckets) {
         bstat[2 * i] = ~0ull;
         bstat[2 * i + 1] = 0;
     }
 }
 
-hipError_t launch_round_init(uint64_t* d_bstat, uint32_t nbuckets, hipStream_t st)
+hipError_t launch_round_init(uint64_t* d_bstat, uint32_t nbuckets, RoundCtl* d_ctl, hipStream_t st)
 {
-    if (nbuckets)
-        k_round_init<<<(nbuckets + 255) / 256, 256, 0, st>>>(d_bstat, nbuckets);
+    k_round_init<<<(nbuckets + 255) / 256 + 1, 256, 0, st>>>(d_bstat, nbuckets, d_ctl);
     return hipGetLastError();
 }
+
+// ------------------------------------------------------------- histogram --
 
 // Bucket sizes per (bucket, chunk) plus per-bucket min/max of the key words
 // (Alg. 1 S_B, and the all-equal test of Alg. 2).  A workgroup of 1024 lanes
@@ -39,6 +43,41 @@ hipError_t launch_round_init(uint64_t* d_bstat, uint32_t nbuckets, hipStream_t s
 // classified, so loads stay in flight through the LDS work.
 constexpr uint32_t kHistThreads = 1024;
 constexpr uint32_t kHistUnroll = 4;
+constexpr uint32_t kPeelMin = 8;   // lanes on one bucket before a wave merges them
+
+// Count one key per valid lane.  When many lanes of the wave hit the same
+// bucket (duplicate-heavy data), same-address LDS atomics serialise lane by
+// lane, so the largest groups are peeled off with two ballots and counted by
+// a single atomic.  Must be called by the whole wave.
+__device__ __forceinline__ void wave_count(uint32_t* h, uint32_t b, bool valid)
+{
+    bool mine = valid;
+    const uint64_t act0 = __ballot(mine);
+    if (act0) {
+        const int lead0 = __ffsll((unsigned long long)act0) - 1;
+        const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)b, lead0);
+        if ((uint32_t)__popcll(__ballot(mine && b == b0)) >= kPeelMin) {
+#pragma unroll 1
+            for (int it = 0; it < 8; ++it) {
+                const uint64_t act = __ballot(mine);
+                if (!act)
+                    break;
+                const int leader = __ffsll((unsigned long long)act) - 1;
+                const uint32_t bl = (uint32_t)__builtin_amdgcn_readlane((int)b, leader);
+                const uint64_t grp = __ballot(mine && b == bl);
+                const uint32_t c = (uint32_t)__popcll(grp);
+                if ((int)__lane_id() == leader)
+                    atomicAdd(&h[bl], c);
+                if (b == bl)
+                    mine = false;
+                if (c < kPeelMin)
+                    break;
+            }
+        }
+    }
+    if (mine)
+        atomicAdd(&h[b], 1u);
+}
 
 template <uint32_t DT, bool MSD>
 __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, const uint64_t* src, uint32_t cnt,
@@ -71,10 +110,11 @@ __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, const 
 #pragma unroll
         for (uint32_t u = 0; u < kHistUnroll; ++u) {
             const uint32_t i = base + u * kHistThreads + threadIdx.x;
-            if (i < cnt) {
-                const uint32_t b = MSD ? msd_bucket<DT>(raw[u], shift, fanout)
-                                       : model_bucket<DT>(M, raw[u], scale, offset, fanout, flags);
-                atomicAdd(&h[b], 1u);
+            const bool valid = i < cnt;
+            const uint32_t b = MSD ? msd_bucket<DT>(raw[u], shift, fanout)
+                                   : model_bucket<DT>(M, raw[u], scale, offset, fanout, flags);
+            wave_count(h, b, valid);
+            if (valid) {
                 // Only a new extreme needs an atomic: min only falls and max
                 // only rises, so a stale read can cause an extra atomic but
                 // never a missed one.
@@ -143,119 +183,7 @@ hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chun
     return hipGetLastError();
 }
 
-// Exclusive scan of u32 counts into u64 positions: block sums, a scan of the
-// block sums, then each block rescans with its offset.
-constexpr uint32_t kScanBlock = 4096;
-
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* in, uint64_t n, uint64_t* sums)
-{
-    __shared__ uint64_t ws[4];
-    uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
-    uint64_t s = 0;
-    for (uint32_t i = threadIdx.x; i < kScanBlock; i += 256) {
-        uint64_t k = base + i;
-        if (k < n)
-            s += in[k];
-    }
-    for (uint32_t d = 32; d > 0; d >>= 1)
-        s += __shfl_xor(s, d, 64);
-    if ((threadIdx.x & 63u) == 0)
-        ws[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
-}
-
-__global__ __launch_bounds__(1024) void k_scan_top(uint64_t* sums, uint32_t nb)
-{
-    __shared__ uint64_t ws[17];
-    const uint32_t per = (nb + 1023) / 1024;
-    const uint32_t lo = min(nb, threadIdx.x * per), hi = min(nb, lo + per);
-    uint64_t s = 0;
-    for (uint32_t i = lo; i < hi; ++i)
-        s += sums[i];
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    uint64_t x = s;
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        uint64_t y = __shfl_up(x, d, 64);
-        if (lane >= d)
-            x += y;
-    }
-    if (lane == 63)
-        ws[wave] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t run = 0;
-        for (uint32_t w = 0; w < 16; ++w) {
-            uint64_t v = ws[w];
-            ws[w] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    uint64_t b = ws[wave] + x - s;
-    for (uint32_t i = lo; i < hi; ++i) {
-        uint64_t v = sums[i];
-        sums[i] = b;
-        b += v;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint64_t n, const uint64_t* sums,
-                                                   uint64_t* out)
-{
-    __shared__ uint64_t ws[5];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
-    constexpr uint32_t per = kScanBlock / 256;
-    uint32_t v[per];
-    uint64_t s = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < per; ++i) {
-        uint64_t k = base + (uint64_t)threadIdx.x * per + i;
-        v[i] = k < n ? in[k] : 0u;
-        s += v[i];
-    }
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    uint64_t x = s;
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        uint64_t y = __shfl_up(x, d, 64);
-        if (lane >= d)
-            x += y;
-    }
-    if (lane == 63)
-        ws[wave] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t run = sums[blockIdx.x];
-        for (uint32_t w = 0; w < 4; ++w) {
-            uint64_t t = ws[w];
-            ws[w] = run;
-            run += t;
-        }
-    }
-    __syncthreads();
-    uint64_t b = ws[wave] + x - s;
-#pragma unroll
-    for (uint32_t i = 0; i < per; ++i) {
-        uint64_t k = base + (uint64_t)threadIdx.x * per + i;
-        if (k < n)
-            out[k] = b;
-        b += v[i];
-    }
-}
-
-size_t scan_tmp_entries(uint64_t n) { return (size_t)((n + kScanBlock - 1) / kScanBlock) + 1; }
-
-hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, hipStream_t st)
-{
-    uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
-    if (!nb)
-        return hipSuccess;
-    k_scan_reduce<<<nb, 256, 0, st>>>(d_in, n, d_tmp);
-    k_scan_top<<<1, 1024, 0, st>>>(d_tmp, nb);
-    k_scan_down<<<nb, 256, 0, st>>>(d_in, n, d_tmp, d_out);
-    return hipGetLastError();
-}
+// -------------------------------------------------------------- classify --
 
 // Classify every bucket of a task: empty, all-equal (filled with its value,
 // never moved again), small (sorted in LDS together with its neighbours) or
@@ -263,35 +191,223 @@ hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64
 // keys; consecutive small buckets whose starts fall into the same window of
 // `thresh` keys form one group, so a group holds fewer than 2*thresh keys.
 // Everything is decided with block-wide scans, no serial walk.
-enum : uint8_t { kEmpty = 0, kSmall = 1, kFillB = 2, kBig = 3 };
+enum : uint8_t { kEmpty = 0, kSmall = 1, kFillB = 2, kBig = 3, kLead = 0x80 };
 
 constexpr int32_t kNone = 0x7fffffff;
 
+__device__ __forceinline__ uint32_t pow2_at_least(uint64_t x)
+{
+    uint32_t p = 1;
+    while (p < x && p < (1u << 30))
+        p <<= 1;
+    return p;
+}
+
+// Fanout of a child range of n keys: many more buckets than needed to bring
+// it under the base threshold (duplicate-heavy ranges need narrow buckets for
+// their repeated keys to end up alone), capped by the caller's fanout.
+__device__ __forceinline__ uint32_t child_fanout(uint64_t n, uint32_t thresh, uint32_t cap)
+{
+    uint32_t f = pow2_at_least((64u * n + thresh - 1) / thresh);
+    f = f < 64u ? 64u : f;
+    return f > cap ? cap : f;
+}
+
+// ---------------------------------------------------------------- layout --
+
+// Lay out the next round on the device (any block size, multiple of 64 up to
+// 1024): chunk size, each task's chunk / bucket / count-matrix offsets, and a
+// training job (sample size, leaves, table offsets) for every task that
+// needs a local model.  The host only reads the totals back.
+constexpr uint32_t kLayoutQ = 9;
+
+__device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& lp, RoundCtl* ctl,
+                              RoundCtl* host_ctl)
+{
+    __shared__ unsigned long long s_keys;
+    __shared__ uint32_t s_maxf, s_maxl, s_maxlev;
+    __shared__ uint64_t wsum[kLayoutQ][16];
+    __shared__ uint64_t carry[kLayoutQ];
+    const uint32_t NT = blockDim.x;
+    const uint32_t nt = ctl->ntasks;
+    if (threadIdx.x == 0) {
+        s_keys = 0;
+        s_maxf = 2;
+        s_maxl = 1;
+        s_maxlev = 0;
+    }
+    if (threadIdx.x < kLayoutQ)
+        carry[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long mykeys = 0;
+    uint32_t maxf = 2, maxl = 1, maxlev = 0;
+    for (uint32_t i = threadIdx.x; i < nt; i += NT) {
+        mykeys += tasks[i].n;
+        maxf = max(maxf, tasks[i].fanout);
+        maxlev = max(maxlev, tasks[i].level);
+        if (tasks[i].kind == kGlobal || tasks[i].kind == kGlobalL1)
+            maxl = max(maxl, tasks[i].leaves);
+    }
+    atomicAdd(&s_keys, mykeys);
+    atomicMax(&s_maxf, maxf);
+    atomicMax(&s_maxl, maxl);
+    atomicMax(&s_maxlev, maxlev);
+    __syncthreads();
+    const uint64_t nkeys = s_keys;
+    uint64_t chunk = (nkeys + kTargetChunks - 1) / kTargetChunks;
+    chunk = (chunk + lp.tile - 1) / lp.tile * lp.tile;
+    chunk = chunk < 4ull * lp.tile ? 4ull * lp.tile : chunk;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    uint32_t my_maxl = 1;
+    for (uint32_t base = 0; base < nt; base += NT) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < nt;
+        Task T{};
+        if (valid)
+            T = tasks[i];
+        const bool local = valid && T.kind == kLocal;
+        uint64_t m = 0;
+        uint32_t L = 0;
+        if (local) {
+            const double want = ceil(lp.rate * (double)T.n);
+            m = want < 1.0 ? 1u : (uint64_t)want;
+            const uint64_t floor_m = T.n < kLocalMinSample ? T.n : kLocalMinSample;
+            m = m > floor_m ? m : floor_m;
+            if (lp.cap && m > lp.cap)
+                m = lp.cap > floor_m ? lp.cap : floor_m;
+            L = (uint32_t)(m < lp.leaves ? m : lp.leaves);
+            my_maxl = max(my_maxl, L);
+        }
+        const uint64_t nch = valid ? (T.n + chunk - 1) / chunk : 0;
+        uint64_t q[kLayoutQ] = {nch,
+                                valid ? T.fanout : 0u,
+                                valid ? (uint64_t)T.fanout * nch : 0u,
+                                valid ? T.n : 0u,
+                                local ? 1u : 0u,
+                                m,
+                                L,
+                                local ? model_doubles(L) : 0u,
+                                local ? (m + 2047) / 2048 : 0u};
+        uint64_t x[kLayoutQ];
+#pragma unroll
+        for (uint32_t j = 0; j < kLayoutQ; ++j) {
+            x[j] = q[j];
+#pragma unroll
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                const uint64_t y = __shfl_up(x[j], d, 64);
+                if (lane >= d)
+                    x[j] += y;
+            }
+            if (lane == 63)
+                wsum[j][wave] = x[j];
+        }
+        __syncthreads();
+        if (threadIdx.x < kLayoutQ) {
+            uint64_t run = carry[threadIdx.x];
+            for (uint32_t w = 0; w < NT / 64; ++w) {
+                const uint64_t v = wsum[threadIdx.x][w];
+                wsum[threadIdx.x][w] = run;
+                run += v;
+            }
+            carry[threadIdx.x] = run;
+        }
+        __syncthreads();
+        uint64_t off[kLayoutQ];
+#pragma unroll
+        for (uint32_t j = 0; j < kLayoutQ; ++j)
+            off[j] = wsum[j][wave] + x[j] - q[j];
+        if (valid) {
+            T.chunk0 = (uint32_t)off[0];
+            T.nchunks = (uint32_t)nch;
+            T.bucket_off = (uint32_t)off[1];
+            T.cnt_off = off[2];
+            T.cnt_base = off[3];
+            if (local) {
+                T.leaves = L;
+                T.model = lp.model_base + off[7];
+                ModelJob J;
+                J.src = (T.src ? T.scratch : T.keys) + T.start;
+                J.n = T.n;
+                J.m = m;
+                J.seed = splitmix64_at(lp.seed ^ (T.start * 0x9e3779b97f4a7c15ull) ^ ((uint64_t)T.seg << 40),
+                                       T.level);
+                J.sample_off = off[5];
+                J.model_off = T.model;
+                J.leaf_off = off[6];
+                J.leaves = L;
+                J.dtype = T.dtype;
+                J.block0 = (uint32_t)off[8];
+                J.nblocks = (uint32_t)((m + 2047) / 2048);
+                jobs[off[4]] = J;
+            }
+            tasks[i] = T;
+        }
+        __syncthreads();
+    }
+    atomicMax(&s_maxl, my_maxl);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->chunk = chunk;
+        ctl->nkeys = nkeys;
+        ctl->chunks = (uint32_t)carry[0];
+        ctl->buckets = (uint32_t)carry[1];
+        ctl->entries = carry[2];
+        ctl->njobs = (uint32_t)carry[4];
+        ctl->samples = carry[5];
+        ctl->leafs = carry[6];
+        ctl->models = carry[7];
+        ctl->blocks = (uint32_t)carry[8];
+        ctl->max_fanout = s_maxf;
+        ctl->max_leaves = s_maxl;
+        ctl->max_level = s_maxlev;
+        __threadfence();
+        *host_ctl = *ctl;      // publish to the host without a copy
+        __threadfence_system();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_layout(Task* tasks, ModelJob* jobs, LayoutParams lp, RoundCtl* ctl,
+                                                RoundCtl* host_ctl)
+{
+    layout_device(tasks, jobs, lp, ctl, host_ctl);
+}
+
+hipError_t launch_layout(Task* d_next, ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* d_ctl, RoundCtl* host_ctl,
+                         hipStream_t st)
+{
+    k_layout<<<1, 256, 0, st>>>(d_next, d_jobs, lp, d_ctl, host_ctl);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_classify(const Task* tasks, const uint64_t* pos, const uint64_t* bstat,
                                                   uint32_t thresh, uint32_t param_fanout, Task* next,
-                                                  Group* groups, Fill* fills, uint8_t* skip,
-                                                  uint32_t* task_flags, RoundCtl* ctl)
+                                                  GroupLists groups, Fill* fills, uint8_t* skip,
+                                                  uint32_t* task_flags, RoundCtl* ctl, ModelJob* jobs,
+                                                  LayoutParams lp, RoundCtl* host_ctl)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Task T = tasks[blockIdx.x];
     const uint32_t f = T.fanout;
-    uint64_t* bst = reinterpret_cast<uint64_t*>(smem);   // bucket start (task-relative)
-    uint64_t* bsz = bst + f;                              // bucket size
-    int32_t* prv = reinterpret_cast<int32_t*>(bsz + f);   // previous non-empty bucket
+    uint64_t* bst = reinterpret_cast<uint64_t*>(smem);   // bucket start (task-relative), f + 1 entries
+    int32_t* prv = reinterpret_cast<int32_t*>(bst + f + 1);
     int32_t* nxt = prv + f;                               // next group breaker (reversed index)
-    uint32_t* gidx = reinterpret_cast<uint32_t*>(nxt + f);
-    uint32_t* tidx = gidx + f;
+    uint32_t* cidx[kGroupClasses];
+    cidx[0] = reinterpret_cast<uint32_t*>(nxt + f);
+    cidx[1] = cidx[0] + f;
+    cidx[2] = reinterpret_cast<uint32_t*>(prv);           // prv is dead once leaders are known
+    uint32_t* tidx = cidx[1] + f;
     uint32_t* fidx = tidx + f;
     uint8_t* kind = reinterpret_cast<uint8_t*>(fidx + f);
-    __shared__ uint32_t ws_u[5];
-    __shared__ int32_t ws_i[5];
-    __shared__ uint32_t s_gb, s_tb, s_fb, s_noprog, s_nfb;
+    __shared__ uint32_t ws_u[17];
+    __shared__ int32_t ws_i[17];
+    __shared__ uint32_t s_gb[kGroupClasses], s_tb, s_fb, s_noprog, s_nfb;
     __shared__ unsigned long long s_fkeys, s_gkeys;
     if (threadIdx.x == 0) {
         s_noprog = 0;
         s_nfb = 0;
         s_fkeys = 0;
         s_gkeys = 0;
+        bst[f] = T.n;
     }
     const uint32_t fill_min = thresh / 8u > 2u ? thresh / 8u : 2u;
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
@@ -310,7 +426,6 @@ __global__ __launch_bounds__(256) void k_classify(const Task* tasks, const uint6
         else
             k = kSmall;
         bst[b] = s0;
-        bsz[b] = sz;
         kind[b] = k;
         prv[b] = sz ? (int32_t)b : -1;
         skip[(uint64_t)T.bucket_off + b] = (k == kFillB);
@@ -325,26 +440,55 @@ __global__ __launch_bounds__(256) void k_classify(const Task* tasks, const uint6
             lead = p < 0 || kind[p] != kSmall || bst[p] / thresh != bst[b] / thresh;
         }
         const bool brk = k != kEmpty && (lead || k != kSmall);
-        gidx[b] = lead ? 1u : 0u;
-        tidx[b] = k == kBig ? 1u : 0u;
-        fidx[b] = k == kFillB ? (uint32_t)((bsz[b] + kFillPiece - 1) / kFillPiece) : 0u;
         nxt[f - 1 - b] = brk ? (int32_t)b : kNone;
-        if (bsz[b] == T.n && (k == kBig || k == kFillB))
+        const uint64_t sz = bst[b + 1] - bst[b];
+        tidx[b] = k == kBig ? 1u : 0u;
+        fidx[b] = k == kFillB ? (uint32_t)((sz + kFillPiece - 1) / kFillPiece) : 0u;
+        if (sz == T.n && (k == kBig || k == kFillB))
             s_noprog = 1;
         if (k == kFillB) {
-            atomicAdd(&s_fkeys, (unsigned long long)bsz[b]);
+            atomicAdd(&s_fkeys, (unsigned long long)sz);
             atomicAdd(&s_nfb, 1u);
         }
         if (k == kSmall)
-            atomicAdd(&s_gkeys, (unsigned long long)bsz[b]);
+            atomicAdd(&s_gkeys, (unsigned long long)sz);
     }
     __syncthreads();
+    // kind[] must only be rewritten once every thread is done reading it
+    for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
+        const int32_t p = prv[b];
+        const uint8_t k = kind[b];
+        const bool lead = k == kSmall && (p < 0 || kind[p] != kSmall || bst[p] / thresh != bst[b] / thresh);
+        prv[b] = lead ? 1 : 0;     // temporary: leader flag
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < f; b += blockDim.x)
+        if (prv[b])
+            kind[b] |= kLead;
+    __syncthreads();
     block_scan_op<int32_t>(nxt, f, kNone, MinI32(), ws_i);   // nxt[f-1-b]: first breaker after b
-    const uint32_t ng = block_scan_u32(gidx, f, ws_u);
+    for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
+        uint32_t c0 = 0, c1 = 0, c2 = 0;
+        if (kind[b] & kLead) {
+            const int32_t e = nxt[f - 1 - b];
+            const uint64_t gsz = (e == kNone ? T.n : bst[e]) - bst[b];
+            c0 = gsz <= kGroupClassCap[0];
+            c1 = !c0 && gsz <= kGroupClassCap[1];
+            c2 = !c0 && !c1;
+        }
+        cidx[0][b] = c0;
+        cidx[1][b] = c1;
+        cidx[2][b] = c2;
+    }
+    __syncthreads();
+    uint32_t ng[kGroupClasses];
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        ng[c] = block_scan_u32(cidx[c], f, ws_u);
     const uint32_t nt = block_scan_u32(tidx, f, ws_u);
     const uint32_t nf = block_scan_u32(fidx, f, ws_u);
     if (threadIdx.x == 0) {
-        s_gb = ng ? atomicAdd(&ctl->ngroups, ng) : 0;
+        for (uint32_t c = 0; c < kGroupClasses; ++c)
+            s_gb[c] = ng[c] ? atomicAdd(&ctl->ngroups[c], ng[c]) : 0;
         s_tb = nt ? atomicAdd(&ctl->ntasks, nt) : 0;
         s_fb = nf ? atomicAdd(&ctl->nfill, nf) : 0;
         if (s_nfb) {
@@ -361,26 +505,22 @@ __global__ __launch_bounds__(256) void k_classify(const Task* tasks, const uint6
     const bool noprog = s_noprog != 0;
     // where the keys of this round's buckets live after the scatter
     const uint64_t* moved = (noprog ? (T.src ? T.scratch : T.keys) : (T.src ? T.keys : T.scratch)) + T.start;
-    const uint32_t lf = 31u - __clz(param_fanout);
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
-        const uint8_t k = kind[b];
-        if (k == kSmall) {
-            const int32_t p = prv[b];
-            const bool lead = p < 0 || kind[p] != kSmall || bst[p] / thresh != bst[b] / thresh;
-            if (!lead)
-                continue;
+        const uint8_t kl = kind[b];
+        const uint8_t k = kl & ~kLead;
+        const uint64_t sz = bst[b + 1] - bst[b];
+        if (kl & kLead) {
             const int32_t e = nxt[f - 1 - b];
-            const uint64_t end = e == kNone ? T.n : bst[e];
             Group G;
             G.src = moved + bst[b];
             G.dst = T.keys + T.start + bst[b];
             G.start = T.start + bst[b];
-            G.n = (uint32_t)(end - bst[b]);
+            G.n = (uint32_t)((e == kNone ? T.n : bst[e]) - bst[b]);
             G.dtype = T.dtype;
-            groups[s_gb + gidx[b]] = G;
+            const uint32_t c = G.n <= kGroupClassCap[0] ? 0u : (G.n <= kGroupClassCap[1] ? 1u : 2u);
+            groups.g[c][s_gb[c] + cidx[c][b]] = G;
         } else if (k == kFillB) {
             const uint64_t raw = from_ord(bstat[2 * ((uint64_t)T.bucket_off + b)], T.dtype);
-            const uint64_t sz = bsz[b];
             const uint32_t np = (uint32_t)((sz + kFillPiece - 1) / kFillPiece);
             for (uint32_t q = 0; q < np; ++q) {
                 Fill F;
@@ -395,21 +535,25 @@ __global__ __launch_bounds__(256) void k_classify(const Task* tasks, const uint6
         } else if (k == kBig) {
             Task C = T;
             C.start = T.start + bst[b];
-            C.n = bsz[b];
+            C.n = sz;
             C.src = noprog ? T.src : 1u - T.src;
             C.level = T.level + 1;
             C.chunk0 = C.nchunks = C.bucket_off = 0;
             C.cnt_off = C.cnt_base = 0;
             const uint64_t lo = bstat[2 * ((uint64_t)T.bucket_off + b)];
             const uint64_t hi = bstat[2 * ((uint64_t)T.bucket_off + b) + 1];
-            const bool stalled = noprog || (T.kind == kLocal && bsz[b] > T.n - T.n / 8u);
+            const bool stalled = noprog || (T.kind == kLocal && sz > T.n - T.n / 8u);
+            const uint32_t fc = child_fanout(sz, thresh, param_fanout);
             if (T.kind == kGlobal) {
-                C.kind = kGlobalL1;             // Alg. 2: level 1 reuses the array's model
-                C.scale = (double)f * (double)f;
-                C.offset = (int64_t)b * (int64_t)f;
+                // Alg. 2 level 1: the array's model again, f1 sub-buckets of bucket b
+                C.kind = kGlobalL1;
+                C.fanout = fc;
+                C.scale = (double)f * (double)fc;
+                C.offset = (int64_t)b * (int64_t)fc;
             } else if (T.kind == kLocal && stalled) {
                 // no model progress: split on the highest differing bit
                 const uint32_t d = 63u - (uint32_t)__clzll((long long)(lo ^ hi));
+                const uint32_t lf = 31u - __clz(fc);
                 uint32_t bits = lf < d + 1 ? lf : d + 1;
                 bits = bits ? bits : 1;
                 C.kind = kMsd;
@@ -419,26 +563,39 @@ __global__ __launch_bounds__(256) void k_classify(const Task* tasks, const uint6
                 C.offset = 0;
                 atomicAdd(&ctl->fallbacks, 1u);
             } else {
-                C.kind = kLocal;                // model trained on the range before the next round
-                C.fanout = param_fanout;
-                C.scale = (double)param_fanout;
+                C.kind = kLocal;       // model trained on the range before the next round
+                C.fanout = fc;
+                C.scale = (double)fc;
                 C.offset = 0;
             }
             next[s_tb + tidx[b]] = C;
         }
     }
+    // The last workgroup to finish lays out the next round.
+    __shared__ uint32_t s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = atomicAdd(&ctl->classified, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        layout_device(next, jobs, lp, ctl, host_ctl);
+    }
 }
 
 hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t* d_pos, const uint64_t* d_bstat,
-                           uint32_t thresh, uint32_t param_fanout, Task* d_next, Group* d_groups, Fill* d_fills,
+                           uint32_t thresh, uint32_t param_fanout, Task* d_next, GroupLists groups, Fill* d_fills,
                            uint8_t* d_skip, uint32_t* d_task_flags, RoundCtl* d_ctl, uint32_t max_fanout,
-                           hipStream_t st)
+                           ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* host_ctl, hipStream_t st)
 {
-    size_t smem = (size_t)max_fanout * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 1) + 16;
-    k_classify<<<ntasks, 256, smem, st>>>(d_tasks, d_pos, d_bstat, thresh, param_fanout, d_next, d_groups,
-                                          d_fills, d_skip, d_task_flags, d_ctl);
+    size_t smem = (size_t)(max_fanout + 1) * 8 + (size_t)max_fanout * (4 + 4 + 4 + 4 + 4 + 4 + 1) + 64;
+    k_classify<<<ntasks, 256, smem, st>>>(d_tasks, d_pos, d_bstat, thresh, param_fanout, d_next, groups,
+                                          d_fills, d_skip, d_task_flags, d_ctl, d_jobs, lp, host_ctl);
     return hipGetLastError();
 }
+
+// --------------------------------------------------------------- scatter --
 
 constexpr uint32_t kScatterThreads = 1024;
 

@@ -19,19 +19,10 @@ __device__ __forceinline__ uint32_t find_job(const ModelJob* jobs, uint32_t njob
     return lo;
 }
 
-__global__ void k_train_init(const ModelJob* jobs, uint32_t njobs, uint64_t* minmax, uint32_t* lcnt,
-                             uint64_t* lmin)
-{
-    const ModelJob J = jobs[blockIdx.x];
-    if (threadIdx.x == 0) {
-        minmax[2 * blockIdx.x] = ~0ull;
-        minmax[2 * blockIdx.x + 1] = 0;
-    }
-    for (uint32_t k = threadIdx.x; k < J.leaves; k += blockDim.x) {
-        lcnt[J.leaf_off + k] = 0;
-        lmin[J.leaf_off + k] = ~0ull;
-    }
-}
+// Training tables use 0 as their neutral value and the fit kernel returns
+// them to 0 after use, so no initialisation pass is needed: per job
+// minmax = {~min, max} of the finite sample words, per leaf lcnt = count and
+// lmin = ~(smallest word).
 
 // Gather the sample (order-preserving words) and reduce its finite range.
 __global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint32_t njobs,
@@ -46,16 +37,23 @@ __global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint
     const ModelJob J = jobs[j];
     const uint64_t t0 = (uint64_t)(blockIdx.x - J.block0) * kSampleBlock;
     uint64_t lo = ~0ull, hi = 0;
-    for (uint32_t i = threadIdx.x; i < kSampleBlock; i += blockDim.x) {
-        uint64_t t = t0 + i;
-        if (t >= J.m)
-            break;
-        uint64_t raw = J.src[sample_index(J.seed, t, J.n)];
-        uint64_t o = to_ord(raw, J.dtype);
-        sample[J.sample_off + t] = o;
-        if (!nonfinite(raw, J.dtype)) {
-            lo = o < lo ? o : lo;
-            hi = o > hi ? o : hi;
+    constexpr uint32_t U = kSampleBlock / 256;    // independent gathers in flight per lane
+    uint64_t raw[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+        const uint64_t t = t0 + u * 256 + threadIdx.x;
+        raw[u] = t < J.m ? J.src[sample_index(J.seed, t, J.n)] : 0;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+        const uint64_t t = t0 + u * 256 + threadIdx.x;
+        if (t < J.m) {
+            const uint64_t o = to_ord(raw[u], J.dtype);
+            sample[J.sample_off + t] = o;
+            if (!nonfinite(raw[u], J.dtype)) {
+                lo = o < lo ? o : lo;
+                hi = o > hi ? o : hi;
+            }
         }
     }
     for (uint32_t d = 32; d > 0; d >>= 1) {
@@ -74,7 +72,7 @@ __global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint
             hi = s_hi[w] > hi ? s_hi[w] : hi;
         }
         if (lo != ~0ull) {
-            atomicMin((unsigned long long*)&minmax[2 * j], (unsigned long long)lo);
+            atomicMax((unsigned long long*)&minmax[2 * j], (unsigned long long)~lo);
             atomicMax((unsigned long long*)&minmax[2 * j + 1], (unsigned long long)hi);
         }
     }
@@ -83,7 +81,7 @@ __global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint
 __device__ __forceinline__ void root_params(const uint64_t* minmax, uint32_t j, uint32_t dt, uint32_t L,
                                             double& xmin, double& xmax, double& rs, bool& any)
 {
-    uint64_t lo = minmax[2 * j], hi = minmax[2 * j + 1];
+    uint64_t lo = ~minmax[2 * j], hi = minmax[2 * j + 1];
     any = lo != ~0ull;
     xmin = any ? ord_value(lo, dt) : 0.0;
     xmax = any ? ord_value(hi, dt) : 0.0;
@@ -139,16 +137,15 @@ __global__ __launch_bounds__(256) void k_train_leaves(const ModelJob* jobs, uint
     for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
         if (c[k]) {
             atomicAdd(&lcnt[J.leaf_off + k], c[k]);
-            atomicMin((unsigned long long*)&lmin[J.leaf_off + k], mn[k]);
+            atomicMax((unsigned long long*)&lmin[J.leaf_off + k], ~mn[k]);
         }
     }
 }
 
 // Fit: knots at leaf minima with exact eCDF values, segments to the next knot.
 // Prefix counts, previous and next non-empty leaf come from block scans.
-__global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const uint64_t* minmax,
-                                                   const uint32_t* lcnt, const uint64_t* lmin,
-                                                   double* models)
+__global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, uint64_t* minmax, uint32_t* lcnt,
+                                                   uint64_t* lmin, double* models)
 {
     __shared__ uint64_t below[kMaxLeaves];
     __shared__ int32_t prv[kMaxLeaves];
@@ -201,11 +198,11 @@ __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const u
             o[3] = yk;
             continue;
         }
-        const double Xk = ord_value(lmin[J.leaf_off + k], J.dtype);
+        const double Xk = ord_value(~lmin[J.leaf_off + k], J.dtype);
         double Xh = xmax, yh = 1.0;
         const int32_t q = nxt[L - 1 - k];          // first non-empty leaf after k
         if (q != 0x7fffffff) {
-            Xh = ord_value(lmin[J.leaf_off + q], J.dtype);
+            Xh = ord_value(~lmin[J.leaf_off + q], J.dtype);
             yh = (double)below[q] / (double)mfin;
         }
         double sl = (yh - yk) / (Xh - Xk);
@@ -216,6 +213,16 @@ __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const u
         o[2] = sl;
         o[3] = yh;
     }
+    __syncthreads();
+    // leave the tables neutral for the next training call
+    for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
+        lcnt[J.leaf_off + k] = 0;
+        lmin[J.leaf_off + k] = 0;
+    }
+    if (threadIdx.x == 0) {
+        minmax[2 * j] = 0;
+        minmax[2 * j + 1] = 0;
+    }
 }
 
 hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t* d_sample,
@@ -224,7 +231,6 @@ hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_b
 {
     if (!njobs)
         return hipSuccess;
-    k_train_init<<<njobs, 256, 0, st>>>(d_jobs, njobs, d_minmax, d_lcnt, d_lmin);
     k_train_sample<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, d_sample, d_minmax);
     k_train_leaves<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, d_sample, d_minmax, d_lcnt, d_lmin);
     k_train_fit<<<njobs, 256, 0, st>>>(d_jobs, d_minmax, d_lcnt, d_lmin, d_models);

@@ -42,7 +42,7 @@ def test_status_strings_host_only():
 def test_default_params_host_only():
     p = ls.params()
     assert p.struct_size == ctypes.sizeof(ls.Params) == 48
-    assert (p.fanout, p.leaves, p.tile, p.base_threshold) == (1024, 1024, 2048, 4096)
+    assert (p.fanout, p.leaves, p.tile, p.base_threshold) == (2048, 1024, 4096, 4096)
     assert p.sample_rate == 0.01
 
 
