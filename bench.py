@@ -71,8 +71,106 @@ def cpu_baseline(a: np.ndarray, sample: int):
                       % (sample, dt)}
 
 
+KERNEL_CLASS_OF = (("k_train", "train"), ("k_hist", "hist"), ("k_scan", "scan"), ("k_classify", "classify"),
+                   ("k_layout", "classify"), ("k_round_init", "classify"), ("k_scatter", "scatter"),
+                   ("k_base", "base"), ("k_fill", "fill"), ("k_touchup", "touchup"))
+
+
+def kernel_class(name: str):
+    for pat, cls in KERNEL_CLASS_OF:
+        if pat in name:
+            return cls
+    return None
+
+
+def summarize_profiles(args):
+    """Turn rocprofv3 databases (a kernel trace, and optionally one FETCH_SIZE
+    and one WRITE_SIZE pass) of a bench run into the text summaries kept in
+    profiles/.  HBM traffic is calibrated against the device-to-device copy of
+    the pristine input that every step makes (a copy of known size)."""
+    import sqlite3
+    wname = args.workload_name
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    con = sqlite3.connect(args.summarize_trace)
+    rows = con.execute("select name, duration from kernels").fetchall()
+    per = {}
+    for name, dur in rows:
+        cls = kernel_class(name) or ("copy" if "copyBuffer" in name else None)
+        short = name.split("(")[0].replace("void ", "").replace("lsort::", "")
+        d = per.setdefault((cls, short), [0, 0.0])
+        d[0] += 1
+        d[1] += dur
+    lines = ["# rocprofv3 kernel trace: %s" % wname, "",
+             "command: " + args.trace_command, "",
+             "%-34s %-9s %6s %12s %12s" % ("kernel", "class", "calls", "total_us", "avg_us")]
+    cls_tot = {}
+    for (cls, short), (n, tot) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        lines.append("%-34s %-9s %6d %12.1f %12.2f" % (short[:34], cls or "-", n, tot / 1e3, tot / n / 1e3))
+        if cls:
+            c = cls_tot.setdefault(cls, [0, 0.0])
+            c[0] += n
+            c[1] += tot
+    lines += ["", "per class (all launches of the class):",
+              "%-9s %6s %12s %12s" % ("class", "calls", "total_us", "avg_us")]
+    for cls, (n, tot) in sorted(cls_tot.items(), key=lambda kv: -kv[1][1]):
+        lines.append("%-9s %6d %12.1f %12.2f" % (cls, n, tot / 1e3, tot / n / 1e3))
+    path = os.path.join(out_dir, "kernels_%s.txt" % wname)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", path)
+    if not (args.summarize_fetch and args.summarize_write):
+        return
+
+    def counter(db, cname):
+        c = sqlite3.connect(db)
+        res = {}
+        for name, did, v in c.execute("select name, dispatch_id, counter_value from pmc_events "
+                                      "where counter_name = ?", (cname,)):
+            res.setdefault(did, [name, 0.0])[1] += v
+        return res
+
+    fetch = counter(args.summarize_fetch, "FETCH_SIZE")
+    write = counter(args.summarize_write, "WRITE_SIZE")
+    copy_bytes = float(args.copy_bytes)
+
+    def scale(vals):
+        # the largest device copy is the n*8-byte restore of the pristine input
+        kib = max(v for name, v in vals.values() if "copyBuffer" in name)
+        return copy_bytes / (kib * 1024.0), kib
+
+    fs, fkib = scale(fetch)
+    ws, wkib = scale(write)
+    cls = args.traffic_kernel
+    fsel = [v for name, v in fetch.values() if kernel_class(name) == cls]
+    wsel = [v for name, v in write.values() if kernel_class(name) == cls]
+    fb = sum(fsel) * 1024.0 * fs / len(fsel)
+    wb = sum(wsel) * 1024.0 * ws / len(wsel)
+    tj = {"kernel": cls, "workload": wname, "kernel_source": kernel_source_hash(),
+          "launches": len(fsel), "fetch_kib_per_launch": sum(fsel) / len(fsel),
+          "write_kib_per_launch": sum(wsel) / len(wsel),
+          "copy_bytes": copy_bytes, "copy_fetch_kib": fkib, "copy_write_kib": wkib,
+          "fetch_scale": fs, "write_scale": ws,
+          "bytes_per_launch": fb + wb, "read_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+          "commands": [args.fetch_command, args.write_command]}
+    path = os.path.join(out_dir, "traffic_%s_%s.json" % (cls, wname))
+    with open(path, "w") as f:
+        json.dump(tj, f, indent=1)
+        f.write("\n")
+    print("wrote", path, json.dumps({k: tj[k] for k in ("fetch_scale", "write_scale", "bytes_per_launch")}))
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--summarize-trace", help="rocprofv3 database of a --kernel-trace run of this script")
+    ap.add_argument("--summarize-fetch", help="rocprofv3 database of a --pmc FETCH_SIZE run")
+    ap.add_argument("--summarize-write", help="rocprofv3 database of a --pmc WRITE_SIZE run")
+    ap.add_argument("--workload-name", default="zipf_lognormal_f64")
+    ap.add_argument("--traffic-kernel", default="scatter")
+    ap.add_argument("--copy-bytes", type=float, default=1.6e9)
+    ap.add_argument("--trace-command", default="")
+    ap.add_argument("--fetch-command", default="")
+    ap.add_argument("--write-command", default="")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
@@ -86,6 +184,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verify", action="store_true", help="check the sorted output against numpy")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_profiles(args)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
