@@ -3,7 +3,7 @@
  *
  * C ABI of the GPU library (liblsort.so).  The method is LearnedSort 2.0
  * (Kristo, Vaidya, Kraska, arXiv 2107.03290): a two-layer linear eCDF model
- * trained on a 1% sample predicts each key's bucket (Sec. 2, Sec. 5.1),
+ * trained on a 1% sample predicts each key's bucket (Sec. 2, Sec. 6.1),
  * keys are partitioned by those predictions (Alg. 1), buckets whose keys
  * are all equal are never partitioned again (Alg. 2, Sec. 4.2), the rest
  * are partitioned again and finally sorted inside the bucket, and a touch-up
@@ -57,7 +57,7 @@ typedef enum { LS_F64 = 1, LS_U64 = 2 } ls_dtype;
 #define LS_FLAG_NONMONOTONE    0x4u   /* test hook: perturb predictions so buckets overlap; the touch-up must repair */
 #define LS_FLAG_PROFILE        0x8u   /* time each kernel class with HIP events (read with ls_last_profile) */
 
-/* Tuning parameters (Sec. 5.1 gives f = 1000, c = 100, L = 1000, 1% sample).
+/* Tuning parameters (Sec. 6.1 gives f = 1000, c = 100, L = 1000, 1% sample).
  * Zero fields take the library defaults.  None of them changes the result. */
 typedef struct {
     uint32_t struct_size;      /* sizeof(ls_params) */
@@ -119,6 +119,30 @@ typedef struct {
 ls_status ls_sort_arrays(ls_ctx* ctx, const ls_array* h_arrays, size_t count, ls_stream_t stream,
                          const ls_params* p);
 
+/* One configuration timed by ls_autotune. */
+typedef struct {
+    uint32_t fanout;
+    uint32_t tile;
+    uint32_t base_threshold;
+    uint32_t reserved;
+    double   ms;               /* fastest repetition; < 0: does not fit this device, not run */
+} ls_tune_result;
+
+/* Autotuner for the GPU-specific knobs (fanout, LDS tile, base-case
+ * threshold; the paper fixes f = 1000, c = 100 for its CPU, Sec. 6.1).
+ * Sorts a library-owned copy of the `count` arrays (HOST list, device keys;
+ * the caller's keys are NOT modified) once per candidate and repetition,
+ * timed with HIP events on `stream`, and writes the fastest configuration to
+ * *best (every other field copied from `base`, which may be NULL).  The
+ * candidates are fanout in {512, 1024, 2048, 4096} x tile in {2048, 4096} x
+ * base_threshold in {1024, 2048, 4096}.  No candidate changes the sorted
+ * result, so tuning only affects speed.  results (HOST, may be NULL) receives
+ * up to cap entries and *n_results the number of candidates.  reps = 0 means
+ * 2.  Synchronous; needs device memory for one more copy of the keys. */
+ls_status ls_autotune(ls_ctx* ctx, const ls_array* h_arrays, size_t count, ls_stream_t stream,
+                      const ls_params* base, uint32_t reps, ls_params* best, ls_tune_result* results,
+                      size_t cap, size_t* n_results);
+
 /* Wait for the context's last sort and report device status bits
  * (LS_DEV_*); device_status may be NULL. */
 ls_status ls_sync(ls_ctx* ctx, uint32_t* device_status);
@@ -142,7 +166,7 @@ const char* ls_last_error(ls_ctx* ctx);
 
 /* ---- stage hooks for parity checks against a reference implementation ---- */
 
-/* Train the global model on the 1% sample of d_keys[0..n) (Sec. 5.1) and
+/* Train the global model on the 1% sample of d_keys[0..n) (Sec. 6.1) and
  * copy it to h_model_out (HOST, cap doubles) in the layout
  * [xmin, xmax, rs, m'] + per leaf [X_k, y_k, yhi_k, s_k] (4 + 4L doubles;
  * an empty leaf has X_k = +inf).  Synchronous. */

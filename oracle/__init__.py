@@ -2,7 +2,7 @@
 
 ctypes binding of ``lsort_oracle.c``: a plain, single-threaded CPU
 implementation of LearnedSort 2.0 (arXiv 2107.03290, Alg. 1 and Alg. 2,
-Sec. 5.1 parameters).  Only the tests, the package smoke check and the
+Sec. 6.1 parameters).  Only the tests, the package smoke check and the
 benchmark's CPU-baseline leg import this module; the GPU library never does.
 """
 from __future__ import annotations
@@ -113,7 +113,7 @@ def _f64(a: np.ndarray):
 
 
 def params(dtype: int = F64, **kw) -> Params:
-    """Paper defaults (Sec. 5.1) overridden by keyword arguments."""
+    """Paper defaults (Sec. 6.1) overridden by keyword arguments."""
     p = Params()
     lib().orc_default_params(ctypes.byref(p), dtype)
     for k, v in kw.items():

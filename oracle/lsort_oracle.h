@@ -7,7 +7,7 @@
  *   - Algorithm 1 (fragment partitioning with a write head),
  *   - Algorithm 2 (two-level driver, homogeneity skip, model-based counting
  *     sort, insertion-sort touch-up),
- *   - Section 5.1 (two-layer model, 1000 leaves, 1% sample, fan-out 1000,
+ *   - Section 6.1 (two-layer model, 1000 leaves, 1% sample, fan-out 1000,
  *     fragment capacity 100).
  *
  * Only the tests, the package smoke check and the benchmark's CPU-baseline
@@ -40,12 +40,12 @@ enum {
 };
 
 typedef struct {
-    uint32_t fanout;           /* f: buckets per partition (Sec. 5.1: 1000) */
-    uint32_t frag_cap;         /* c: fragment capacity (Sec. 5.1: 100) */
-    uint32_t leaves;           /* L: leaf models of the two-layer model (Sec. 5.1: 1000) */
+    uint32_t fanout;           /* f: buckets per partition (Sec. 6.1: 1000) */
+    uint32_t frag_cap;         /* c: fragment capacity (Sec. 6.1: 100) */
+    uint32_t leaves;           /* L: leaf models of the two-layer model (Sec. 6.1: 1000) */
     uint32_t small_n;          /* n <= small_n: insertion sort only (0 -> 2*f) */
     uint64_t s_max;            /* 0: paper-literal two levels; else recurse into sub-buckets > s_max */
-    double   sample_rate;      /* Sec. 5.1: 1% */
+    double   sample_rate;      /* Sec. 6.1: 1% */
     uint64_t sample_cap;       /* 0: no cap on the global sample size */
     uint64_t seed;             /* seed of the SplitMix64 sample stream */
     uint32_t local_min_sample; /* minimum sample of a local (recursion) model */
@@ -72,7 +72,7 @@ void orc_default_params(orc_params* p, uint32_t dtype);
 /* Sort keys (raw f64 bits or u64 words) in place. */
 int orc_sort(uint64_t* keys, size_t n, const orc_params* p, orc_stats* st);
 
-/* Sample size m for n keys and the t-th sample index (Sec. 5.1, 1% sample). */
+/* Sample size m for n keys and the t-th sample index (Sec. 6.1, 1% sample). */
 uint64_t orc_sample_size(uint64_t n, double rate, uint64_t cap);
 uint64_t orc_sample_index(uint64_t seed, uint64_t t, uint64_t n);
 uint64_t orc_splitmix64_at(uint64_t seed, uint64_t t);

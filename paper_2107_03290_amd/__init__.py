@@ -39,7 +39,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime er
 # C-ABI entry points declared in include/lsort.h
 EXPORTS = (
     "ls_create", "ls_destroy", "ls_default_params", "ls_workspace_size", "ls_reserve",
-    "ls_sort_f64", "ls_sort_u64", "ls_sort_segments", "ls_sort_arrays", "ls_sync",
+    "ls_sort_f64", "ls_sort_u64", "ls_sort_segments", "ls_sort_arrays", "ls_autotune", "ls_sync",
     "ls_last_stats", "ls_last_profile", "ls_profile_reset", "ls_status_string", "ls_last_error",
     "ls_model_train", "ls_stage_hist",
     "ls_server_create", "ls_server_submit", "ls_server_wait", "ls_server_stats",
@@ -72,6 +72,11 @@ class Array(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("fanout", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("base_threshold", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("ms", ctypes.c_double)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -97,6 +102,8 @@ def lib() -> ctypes.CDLL:
             L.ls_sort_u64.argtypes = [vp, vp, sz, vp, P(Params)]
             L.ls_sort_segments.argtypes = [vp, ctypes.c_int, vp, P(u64), sz, P(ctypes.c_uint8), vp, P(Params)]
             L.ls_sort_arrays.argtypes = [vp, P(Array), sz, vp, P(Params)]
+            L.ls_autotune.argtypes = [vp, P(Array), sz, vp, P(Params), ctypes.c_uint32, P(Params),
+                                      P(TuneResult), sz, P(sz)]
             L.ls_sync.argtypes = [vp, P(ctypes.c_uint32)]
             L.ls_last_stats.argtypes = [vp, P(u64)]
             L.ls_last_profile.argtypes = [vp, P(ctypes.c_double), sz]
@@ -207,6 +214,35 @@ class Sorter:
         self._check(lib().ls_sort_arrays(self._ctx, arr, len(tensors), st, _pp(p)))
         return tensors
 
+    def autotune(self, tensors: Sequence, offsets: Sequence[int] | None = None, p: Params | None = None,
+                 reps: int = 2):
+        """Time the candidate (fanout, tile, base_threshold) settings on a
+        copy of the keys (left unmodified) and return (best Params, results).
+        `tensors` is a list of device tensors, or one tensor split by
+        `offsets` into segments."""
+        if offsets is not None:
+            (t,) = tensors if isinstance(tensors, (list, tuple)) else (tensors,)
+            _check_tensor(t)
+            code, base = _dtype_code(t), t.data_ptr()
+            arr = (Array * (len(offsets) - 1))()
+            for i in range(len(offsets) - 1):
+                arr[i] = Array(base + 8 * int(offsets[i]), int(offsets[i + 1]) - int(offsets[i]), code, 0)
+            st = _stream_handle(t)
+        else:
+            arr = (Array * len(tensors))()
+            for i, t in enumerate(tensors):
+                _check_tensor(t)
+                arr[i] = Array(t.data_ptr(), t.numel(), _dtype_code(t), 0)
+            st = _stream_handle(tensors[0]) if len(tensors) else None
+        best = Params()
+        res = (TuneResult * 64)()
+        cnt = ctypes.c_size_t()
+        self._check(lib().ls_autotune(self._ctx, arr, len(arr), st, _pp(p), reps, ctypes.byref(best), res, 64,
+                                      ctypes.byref(cnt)))
+        out = [dict(fanout=r.fanout, tile=r.tile, base_threshold=r.base_threshold, ms=r.ms)
+               for r in res[:min(cnt.value, 64)]]
+        return best, out
+
     def sync(self) -> int:
         s = ctypes.c_uint32()
         self._check(lib().ls_sync(self._ctx, ctypes.byref(s)))
@@ -285,6 +321,56 @@ def sort_segments_(t, offsets, dtypes=None, p: Params | None = None):
 
 def sort_arrays_(tensors, p: Params | None = None):
     return _sorter(tensors[0].device.index or 0).sort_arrays_(tensors, p)
+
+
+class TuneCache:
+    """Autotuned parameters per size class, kept in a JSON file.
+
+    The class of a batch is (key type, log2 of its total keys, log2 of its
+    mean array size), so one measurement serves every batch of that shape.
+    Tuned parameters never change a sorted result, only its speed."""
+
+    def __init__(self, path: str):
+        import json
+        self.path = path
+        self.table = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                self.table = json.load(f)
+
+    @staticmethod
+    def size_class(dtype: int, total: int, count: int) -> str:
+        mean = total // max(count, 1)
+        return "%s:t%d:m%d" % ("f64" if dtype == F64 else "u64", max(total, 1).bit_length() - 1,
+                               max(mean, 1).bit_length() - 1)
+
+    def lookup(self, key: str) -> Params | None:
+        e = self.table.get(key)
+        if e is None:
+            return None
+        return params(fanout=e["fanout"], tile=e["tile"], base_threshold=e["base_threshold"])
+
+    def tuned(self, sorter: Sorter, tensors: Sequence, offsets: Sequence[int] | None = None,
+              p: Params | None = None, reps: int = 2) -> Params:
+        """Cached parameters for this batch's class, tuning (and saving) on a miss."""
+        import json
+        if offsets is not None:
+            t = tensors[0] if isinstance(tensors, (list, tuple)) else tensors
+            dt, total, count = _dtype_code(t), int(offsets[-1]), len(offsets) - 1
+        else:
+            dt, total, count = _dtype_code(tensors[0]), sum(int(t.numel()) for t in tensors), len(tensors)
+        key = self.size_class(dt, total, count)
+        got = self.lookup(key)
+        if got is not None:
+            return got
+        best, results = sorter.autotune(tensors, offsets, p, reps)
+        self.table[key] = {"fanout": best.fanout, "tile": best.tile, "base_threshold": best.base_threshold,
+                           "results": results}
+        d = os.path.dirname(os.path.abspath(self.path))
+        os.makedirs(d, exist_ok=True)
+        with open(self.path, "w") as f:
+            json.dump(self.table, f, indent=1)
+        return self.lookup(key)
 
 
 class Server:

@@ -1,7 +1,7 @@
 // Host side of the LearnedSort 2.0 pipeline and the C ABI (include/lsort.h).
 //
 // One sort (or one batch of arrays) runs as:
-//   train   global models on a 1% sample of each large array (Sec. 5.1),
+//   train   global models on a 1% sample of each large array (Sec. 6.1),
 //   rounds  histogram -> scan -> classify -> layout -> scatter over every
 //           task of the round (Alg. 1 as a count-then-place partition; the
 //           next round's task list is built and laid out on the device, the
@@ -71,7 +71,7 @@ uint32_t group_class(uint32_t n)
 struct ls_ctx {
     int device = 0;
     std::string err;
-    DevBuf scratch, models, sample, minmax, lcnt, lmin, gjobs, ljobs, tasks, next, cnt, pos, scantmp, bstat,
+    DevBuf scratch, tune, models, sample, minmax, lcnt, lmin, gjobs, ljobs, tasks, next, cnt, pos, scantmp, bstat,
         skip, tflags, fills, ctl;
     DevBuf groups[kGroupClasses];
     PinBuf pin_tasks, pin_jobs, pin_groups[kGroupClasses];
@@ -590,7 +590,7 @@ ls_status ls_destroy(ls_ctx* C)
         return LS_ERR_INVALID;
     (void)hipSetDevice(C->device);
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&C->scratch, &C->models, &C->sample, &C->minmax, &C->lcnt, &C->lmin, &C->gjobs,
+    DevBuf* bufs[] = {&C->scratch, &C->tune, &C->models, &C->sample, &C->minmax, &C->lcnt, &C->lmin, &C->gjobs,
                       &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
                       &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2]};
     for (DevBuf* b : bufs)
@@ -685,6 +685,119 @@ ls_status ls_sort_arrays(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_s
     for (size_t i = 0; i < count; ++i)
         a.push_back(Array{(uint64_t*)h_arrays[i].d_keys, nullptr, h_arrays[i].n, h_arrays[i].dtype});
     return sort_arrays(C, a, (hipStream_t)stream, p);
+}
+
+ls_status ls_autotune(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_stream_t stream, const ls_params* base,
+                      uint32_t reps, ls_params* best, ls_tune_result* results, size_t cap, size_t* n_results)
+{
+    if (!C || !best || (count && !h_arrays))
+        return LS_ERR_INVALID;
+    ls_params bp;
+    if (base) {
+        if (base->struct_size != sizeof(ls_params))
+            return fail(C, LS_ERR_INVALID, "ls_params.struct_size mismatch");
+        bp = *base;
+    } else {
+        ls_default_params(&bp);
+    }
+    Params P0;
+    TRY(resolve(C, &bp, P0));
+    uint64_t total = 0;
+    for (size_t i = 0; i < count; ++i) {
+        if (h_arrays[i].n && !h_arrays[i].d_keys)
+            return fail(C, LS_ERR_INVALID, "null key pointer with n > 0");
+        if (h_arrays[i].dtype != LS_F64 && h_arrays[i].dtype != LS_U64)
+            return fail(C, LS_ERR_INVALID, "unknown dtype");
+        total += h_arrays[i].n;
+    }
+    reps = reps ? reps : 2;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(C, hipSetDevice(C->device));
+    TRY(ensure(C, C->tune, std::max<uint64_t>(total, 1) * 8, st));
+    // the copies sit back to back in the tuning buffer; arrays that are
+    // already back to back in the caller's memory are restored with one copy
+    std::vector<ls_array> copies(count);
+    std::vector<std::pair<size_t, size_t>> runs;  // [first, last) arrays contiguous in the source
+    uint64_t off = 0;
+    for (size_t i = 0; i < count; ++i) {
+        copies[i] = h_arrays[i];
+        copies[i].d_keys = (uint64_t*)C->tune.p + off;
+        off += h_arrays[i].n;
+        const bool joins = i > 0 && (const uint64_t*)h_arrays[i - 1].d_keys + h_arrays[i - 1].n ==
+                                        (const uint64_t*)h_arrays[i].d_keys;
+        if (joins)
+            runs.back().second = i + 1;
+        else
+            runs.push_back({i, i + 1});
+    }
+    hipEvent_t e0, e1;
+    HIPCHECK(C, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(C, LS_ERR_HIP, "hipEventCreate failed");
+    }
+    static const uint32_t fanouts[] = {512, 1024, 2048, 4096};
+    static const uint32_t tiles[] = {2048, 4096};
+    static const uint32_t bases[] = {1024, 2048, 4096};
+    size_t k = 0;
+    double best_ms = -1.0;
+    ls_status rc = LS_OK;
+    for (uint32_t f : fanouts)
+        for (uint32_t t : tiles)
+            for (uint32_t b : bases) {
+                ls_params cp = bp;
+                cp.fanout = f;
+                cp.tile = t;
+                cp.base_threshold = b;
+                cp.flags &= ~(LS_FLAG_PROFILE | LS_FLAG_SYNC);
+                Params P;
+                double ms = -1.0;
+                if (resolve(C, &cp, P) == LS_OK) {
+                    for (uint32_t r = 0; r < reps && rc == LS_OK; ++r) {
+                        for (auto& run : runs) {
+                            uint64_t n = 0;
+                            for (size_t i = run.first; i < run.second; ++i)
+                                n += h_arrays[i].n;
+                            if (n && hipMemcpyAsync(copies[run.first].d_keys, h_arrays[run.first].d_keys, n * 8,
+                                                    hipMemcpyDeviceToDevice, st) != hipSuccess)
+                                rc = fail(C, LS_ERR_HIP, "copy for tuning failed");
+                        }
+                        std::vector<Array> a;
+                        a.reserve(count);
+                        for (auto& c : copies)
+                            a.push_back(Array{(uint64_t*)c.d_keys, nullptr, c.n, c.dtype});
+                        if (rc == LS_OK && hipEventRecord(e0, st) != hipSuccess)
+                            rc = fail(C, LS_ERR_HIP, "hipEventRecord failed");
+                        if (rc == LS_OK)
+                            rc = sort_arrays(C, a, st, &cp);
+                        float el = 0.f;
+                        if (rc == LS_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                                            hipEventSynchronize(e1) != hipSuccess ||
+                                            hipEventElapsedTime(&el, e0, e1) != hipSuccess))
+                            rc = fail(C, LS_ERR_HIP, "timing failed");
+                        if (rc == LS_OK && (ms < 0 || el < ms))
+                            ms = el;
+                    }
+                }
+                if (rc != LS_OK)
+                    break;
+                if (results && k < cap)
+                    results[k] = ls_tune_result{f, t, b, 0, ms};
+                ++k;
+                if (ms >= 0 && (best_ms < 0 || ms < best_ms)) {
+                    best_ms = ms;
+                    *best = cp;
+                    best->flags = bp.flags;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TRY(rc);
+    if (best_ms < 0)
+        *best = bp;
+    if (n_results)
+        *n_results = k;
+    return LS_OK;
 }
 
 ls_status ls_sync(ls_ctx* C, uint32_t* device_status)

@@ -1,4 +1,4 @@
-// Model training: sample, per-leaf statistics, spline fit (Sec. 5.1).
+// Model training: sample, per-leaf statistics, spline fit (Sec. 6.1).
 #include "lsort_device.h"
 
 #pragma clang fp contract(off)

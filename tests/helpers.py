@@ -52,3 +52,22 @@ def fingerprint(words: np.ndarray) -> tuple:
 
 
 SPECIAL_F64 = np.array([-np.inf, -1.5, -0.0, 0.0, 5e-324, 1.0, 2.0 ** 53, np.inf])
+
+
+def fingerprint_chunked(words: np.ndarray, chunk: int = 1 << 25) -> tuple:
+    """fingerprint() of a large array, computed piece by piece."""
+    s, x = 0, 0
+    for lo in range(0, words.size, chunk):
+        _, ps, px = fingerprint(words[lo:lo + chunk])
+        s = (s + ps) & ((1 << 64) - 1)
+        x ^= px
+    return (int(words.size), s, x)
+
+
+def is_sorted_words(o: np.ndarray, chunk: int = 1 << 26) -> bool:
+    """Adjacent order words non-decreasing, checked piece by piece."""
+    for lo in range(0, max(o.size - 1, 0), chunk):
+        hi = min(o.size, lo + chunk + 1)
+        if not np.all(o[lo + 1:hi] >= o[lo:hi - 1]):
+            return False
+    return True

@@ -1,0 +1,77 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (default parameters, profiling events on).
+
+2e8 Zipf f64: the whole output against a library sort of the order words.
+1e9 mixed u64: too large for a host sort inside a test, so it is checked by
+properties that fix the result at any size (non-decreasing, same multiset by
+fingerprint) plus sampled outputs whose rank is counted directly in the input.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import expected_sorted, fingerprint_chunked, is_sorted_words, raw_words
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+ls = pytest.importorskip("paper_2107_03290_amd")
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = ls.Sorter(0)
+    yield s
+    s.close()
+
+
+def upload(a: np.ndarray):
+    w = raw_words(a).view(np.int64)
+    t = torch.empty(a.size, dtype=torch.int64, device="cuda:0")
+    step = 1 << 26
+    for lo in range(0, a.size, step):
+        t[lo:lo + step].copy_(torch.from_numpy(w[lo:lo + step]))
+    return t.view(torch.float64) if a.dtype == np.float64 else t
+
+
+def download(t) -> np.ndarray:
+    return t.view(torch.int64).cpu().numpy().view(np.uint64)
+
+
+def test_zipf_lognormal_200m_exact(S):
+    a = W.zipf_lognormal(200_000_000, seed=2)
+    t = upload(a)
+    S.sort_(t, ls.params(flags=ls.FLAG_PROFILE))
+    torch.cuda.synchronize()
+    got = download(t)
+    del t
+    assert np.array_equal(got, expected_sorted(a))
+    st = S.last_stats()
+    assert st["seams_repaired"] == 0
+
+
+def test_mixed_u64_1e9_properties(S):
+    n = 1_000_000_000
+    a = W.mixed_u64(n, seed=3)
+    fp_in = fingerprint_chunked(a)
+    t = upload(a)
+    S.sort_(t, ls.params(flags=ls.FLAG_PROFILE))
+    torch.cuda.synchronize()
+    got = download(t)
+    del t
+    torch.cuda.empty_cache()
+    assert is_sorted_words(got)
+    assert fingerprint_chunked(got) == fp_in
+    # sampled outputs: position p holds the key v with #(< v) <= p < #(<= v)
+    r = np.random.default_rng(11)
+    for p in np.concatenate([[0, n - 1, n // 3, 2 * n // 3], r.integers(0, n, size=6)]):
+        v = got[int(p)]
+        lt = le = 0
+        for lo in range(0, n, 1 << 27):
+            c = a[lo:lo + (1 << 27)]
+            lt += int(np.count_nonzero(c < v))
+            le += int(np.count_nonzero(c <= v))
+        assert lt <= int(p) < le, (int(p), int(v))
+    assert S.last_stats()["seams_repaired"] == 0

@@ -36,7 +36,7 @@ def test_splitmix64_published_outputs():
 
 @pytest.mark.parametrize("n", [1, 7, 99, 100, 101, 12345, 1_000_000, 200_000_000, 10 ** 9, 2 ** 40 + 3])
 def test_sample_size_is_ceil_one_percent(n):
-    # Sec. 5.1: 1% sample; reading R16: m = max(1, ceil(n/100)).
+    # Sec. 6.1: 1% sample; reading R16: m = max(1, ceil(n/100)).
     assert oracle.lib().orc_sample_size(n, 0.01, 0) == max(1, -(-n // 100))
 
 
@@ -385,7 +385,7 @@ def test_touchup_moves_small_on_smooth_input():
 # --------------------------------------------------------------- generators --
 
 def test_twodups_duplicate_ratio_near_paper():
-    # Sec. 5.4 states 89% duplicates for TwoDups (N unstated).
+    # Sec. 6.4 states 89% duplicates for TwoDups (N unstated).
     d = W.duplicate_ratio(W.two_dups(1_000_000))
     assert 0.80 <= d <= 0.96
 

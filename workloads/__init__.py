@@ -14,13 +14,15 @@ Workloads (sizes as used by the tests and the benchmark):
                     family per array: uniform, normal, lognormal, zipf-dup.
   requests          a Poisson stream of f64 / u64 sort requests, sizes
                     log-uniform in [1024, 67108864], duplicate ratio U(0, 0.99).
-Paper families (Sec. 5.1 list of synthetic datasets): root_dups, two_dups,
+Paper families (Sec. 6.1 list of synthetic datasets): root_dups, two_dups,
 mix_gauss, normal, lognormal(0, 0.5), chi_square(4), exponential(2),
 uniform(0..N), zipf(skew).
 """
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -47,6 +49,25 @@ def zipf_table(distinct: int, s: float) -> np.ndarray:
     return c / c[-1]
 
 
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(n: int, fill, workers: int | None = None) -> None:
+    """Run fill(c, lo, hi) for every CHUNK-sized piece of [0, n), in threads
+    (numpy's generators and ufuncs release the GIL on large arrays).  Each
+    piece draws from its own stream, so the result does not depend on the
+    number of threads."""
+    pieces = [(c, lo, min(n, lo + CHUNK)) for c, lo in enumerate(range(0, n, CHUNK))]
+    w = workers or _workers()
+    if w == 1 or len(pieces) == 1:
+        for c, lo, hi in pieces:
+            fill(c, lo, hi)
+        return
+    with ThreadPoolExecutor(w) as ex:
+        list(ex.map(lambda t: fill(*t), pieces))
+
+
 def zipf_lognormal(n: int = 200_000_000, seed: int = 2, distinct: int = 100_000,
                    s: float = 1.2, sigma: float = 2.0) -> np.ndarray:
     """Zipf(s)-distributed picks among `distinct` lognormal(0, sigma) values."""
@@ -54,36 +75,48 @@ def zipf_lognormal(n: int = 200_000_000, seed: int = 2, distinct: int = 100_000,
     values = r.lognormal(0.0, sigma, size=distinct)
     cdf = zipf_table(distinct, s)
     out = np.empty(n, dtype=np.float64)
-    for lo in range(0, n, CHUNK):
-        hi = min(n, lo + CHUNK)
-        rank = np.searchsorted(cdf, r.random(hi - lo), side="right")
+
+    def fill(c, lo, hi):
+        rank = np.searchsorted(cdf, _rng(seed, 1 + c).random(hi - lo), side="right")
         np.minimum(rank, distinct - 1, out=rank)
         out[lo:hi] = values[rank]
+
+    _chunked(n, fill)
     return out
 
 
 def mixed_u64(n: int = 1_000_000_000, seed: int = 3) -> np.ndarray:
-    """Equal thirds (the first takes the remainder) of three u64 families,
-    placed at uniformly shuffled positions."""
+    """Equal thirds (the first takes the remainder) of three u64 families at
+    uniformly random positions: the exact family counts of each CHUNK-sized
+    piece are drawn hypergeometrically, then shuffled inside the piece, which
+    places the thirds as a global shuffle would."""
     r = _rng(seed)
-    sizes = [n - 2 * (n // 3), n // 3, n // 3]
-    label = np.repeat(np.arange(3, dtype=np.uint8), sizes)
-    r.shuffle(label)
+    left = np.array([n - 2 * (n // 3), n // 3, n // 3], dtype=np.int64)
+    counts = []
+    for lo in range(0, n, CHUNK):
+        k = min(n, lo + CHUNK) - lo
+        if k < left.sum():
+            c0 = r.hypergeometric(left[0], left[1] + left[2], k) if left[0] else 0
+            c1 = r.hypergeometric(left[1], left[2], k - c0) if left[1] and k > c0 else 0
+            c = np.array([c0, c1, k - c0 - c1], dtype=np.int64)
+        else:
+            c = left.copy()
+        left -= c
+        counts.append(c)
     out = np.empty(n, dtype=np.uint64)
-    for fam in range(3):
-        pos = np.flatnonzero(label == fam)
-        for lo in range(0, pos.size, CHUNK):
-            hi = min(pos.size, lo + CHUNK)
-            k = hi - lo
-            if fam == 0:
-                v = np.rint(r.normal(2.0 ** 40, 2.0 ** 36, size=k))
-                v = np.clip(v, 0, 2.0 ** 63).astype(np.uint64)
-            elif fam == 1:
-                v = np.rint(r.exponential(2.0 ** 30, size=k)).astype(np.uint64)
-            else:
-                v = r.integers(0, 2 ** 64, size=k, dtype=np.uint64, endpoint=False) % np.uint64(10_000)
-            out[pos[lo:hi]] = v
-        del pos
+
+    def fill(c, lo, hi):
+        g = _rng(seed, 1 + c)
+        k0, k1, k2 = (int(v) for v in counts[c])
+        v = np.empty(hi - lo, dtype=np.uint64)
+        a = np.rint(g.normal(2.0 ** 40, 2.0 ** 36, size=k0))
+        v[:k0] = np.clip(a, 0, 2.0 ** 63).astype(np.uint64)
+        v[k0:k0 + k1] = np.rint(g.exponential(2.0 ** 30, size=k1)).astype(np.uint64)
+        v[k0 + k1:] = g.integers(0, 2 ** 64, size=k2, dtype=np.uint64, endpoint=False) % np.uint64(10_000)
+        g.shuffle(v)
+        out[lo:hi] = v
+
+    _chunked(n, fill)
     return out
 
 
@@ -151,13 +184,23 @@ def segment_keys(spec: SegmentSpec, i: int) -> np.ndarray:
     return zipf_dup(r, k, float(spec.dup_ratio[i]))
 
 
-def segments(spec: SegmentSpec, out: np.ndarray | None = None) -> np.ndarray:
+def segments(spec: SegmentSpec, out: np.ndarray | None = None, workers: int | None = None) -> np.ndarray:
+    """All segments back to back (each from its own stream, in threads)."""
     total = int(spec.sizes.sum())
     if out is None:
         out = np.empty(total, dtype=np.float64)
     off = spec.offsets
-    for i in range(spec.sizes.size):
+
+    def fill(i):
         out[int(off[i]):int(off[i + 1])] = segment_keys(spec, i)
+
+    w = workers or _workers()
+    if w == 1:
+        for i in range(spec.sizes.size):
+            fill(i)
+    else:
+        with ThreadPoolExecutor(w) as ex:
+            list(ex.map(fill, range(spec.sizes.size)))
     return out
 
 
