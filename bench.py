@@ -71,6 +71,223 @@ def cpu_baseline(a: np.ndarray, sample: int):
                       % (sample, dt)}
 
 
+def roofline(prof: dict, wname: str) -> dict:
+    """Roofline entry of the dominant kernel class: algorithmic bytes per
+    launch over the average launch time (HIP events on the sort's stream)."""
+    dom = max(("hist", "scatter", "base", "fill", "train"), key=lambda k: prof[k][0])
+    ms, launches, byt = prof[dom]
+    achieved = (byt / launches) / ((ms / launches) / 1e3) / 1e9 if launches else 0.0
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (dom, wname))
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        if tj.get("kernel_source") == kernel_source_hash():
+            traffic = tj.get("bytes_per_launch")
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "alg_bytes_per_launch": byt / launches if launches else 0.0,
+            "avg_launch_ms": ms / launches if launches else 0.0}
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else 0.0
+
+
+def bench_segments(args, torch, ls):
+    """10,000 f64 arrays (log-uniform sizes 1,024..4,194,304, four families)
+    sorted as one batch with autotuned parameters, against one plain sort
+    call per array on the same GPU.  Both must give identical bits."""
+    import workloads as W
+    spec = W.segment_spec(count=args.segments)
+    t0 = time.perf_counter()
+    keys = W.segments(spec)
+    off = spec.offsets
+    n = int(off[-1])
+    print("segments: %d arrays, %d keys generated in %.1f s" % (off.size - 1, n, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    pristine = to_device(keys, torch)
+    work = torch.empty_like(pristine)
+    S = ls.Sorter(0)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    best, results = S.autotune([pristine], offsets=off, reps=1)
+    t_tune = time.perf_counter() - t0
+    tuned = ls.params(fanout=best.fanout, tile=best.tile, base_threshold=best.base_threshold,
+                      flags=ls.FLAG_PROFILE)
+    print("autotune: fanout %d tile %d base %d (%.1f s)" % (best.fanout, best.tile, best.base_threshold, t_tune),
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        work.copy_(pristine)
+        S.sort_segments_(work, off, p=tuned)
+    torch.cuda.synchronize()
+    S.profile_reset()
+    K = args.steps
+    ms_b = []
+    for _ in range(K):
+        work.copy_(pristine)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        S.sort_segments_(work, off, p=tuned)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_b.append(e0.elapsed_time(e1))
+    prof = S.profile()
+    stats = S.last_stats()
+    # plain: one call per array, default parameters, same stream
+    plain = pristine.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(off.size - 1):
+        S.sort_(plain[int(off[i]):int(off[i + 1])])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1)
+    same = bool(torch.equal(work.view(torch.int64), plain.view(torch.int64)))
+    if not same:
+        raise SystemExit("batched and plain results differ")
+    ms = sum(ms_b) / K
+    line = {
+        "metric": METRIC, "value": n / (ms / 1e3), "unit": "keys/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator; no dataset)",
+        "config": {"workload": "segments_%d_f64" % (off.size - 1), "keys": n, "fanout": best.fanout,
+                   "tile": best.tile, "base_threshold": best.base_threshold, "autotune_s": t_tune},
+        "plain": {"value": n / (ms_p / 1e3), "unit": "keys/s", "ms": ms_p,
+                  "calls": int(off.size - 1), "params": "defaults"},
+        "batched_over_plain": ms_p / ms,
+        "identical_to_plain": same,
+        "roofline": roofline(prof, "segments_%d_f64" % (off.size - 1)),
+        "kernel_ms_per_step": {k: prof[k][0] / K for k in prof},
+        "pipeline": stats,
+        "autotune": results,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        take = int(np.searchsorted(off, min(args.cpu_sample, n), side="right")) - 1
+        take = max(take, 1)
+        t0 = time.perf_counter()
+        for i in range(take):
+            oracle.sort(keys[int(off[i]):int(off[i + 1])].copy(), s_max=4096)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": int(off[take]) / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+                                "sample": "first %d arrays (%d keys), single-threaded C oracle, %.1f s"
+                                          % (take, int(off[take]), dt)}
+    print(json.dumps(line), flush=True)
+    S.close()
+
+
+def bench_served(args, torch, ls):
+    """A stream of f64 / u64 sort requests (sizes log-uniform 1,024..2^26,
+    duplicate ratio U(0, 0.99)) served by the continuous-batching server
+    against one-request-at-a-time plain sorting, first as a burst (all
+    requests queued at once: throughput), then with Poisson arrivals at 80%
+    of the plain rate (latency).  Every served result must equal the plain
+    one."""
+    import threading
+    import workloads as W
+    from concurrent.futures import ThreadPoolExecutor
+    R = args.requests
+    spec = W.request_spec()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(16) as ex:
+        reqs = list(ex.map(lambda i: W.request_keys(spec, i), range(R)))
+    total = int(sum(a.size for a in reqs))
+    print("served: %d requests, %d keys generated in %.1f s" % (R, total, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    pristine = [to_device(a, torch) for a in reqs]
+    work = [torch.empty_like(t) for t in pristine]
+    ref = [torch.empty_like(t) for t in pristine]
+    S = ls.Sorter(0)
+
+    def restore(dst):
+        for d, p in zip(dst, pristine):
+            d.copy_(p)
+        torch.cuda.synchronize()
+
+    # warm-up both paths (buffers grow once)
+    restore(ref)
+    for t in ref[:8]:
+        S.sort_(t)
+    torch.cuda.synchronize()
+
+    def run_plain(arrival):
+        restore(ref)
+        lat = []
+        start = time.perf_counter()
+        for t, a in zip(ref, arrival):
+            now = time.perf_counter() - start
+            if now < a:
+                time.sleep(a - now)
+            S.sort_(t)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - start - a)
+        return time.perf_counter() - start, lat
+
+    def run_served(arrival):
+        restore(work)
+        srv = ls.Server(0, hbm_budget=args.budget_gb << 30, max_inflight=args.inflight)
+        tickets = [None] * R
+        sub_t = [0.0] * R
+        start = time.perf_counter()
+
+        def submitter():
+            for i, a in enumerate(arrival):
+                now = time.perf_counter() - start
+                if now < a:
+                    time.sleep(a - now)
+                sub_t[i] = time.perf_counter() - start
+                tickets[i] = srv.submit(work[i])
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join() if arrival[-1] == 0 else None
+        lat = []
+        for i in range(R):
+            while tickets[i] is None:
+                time.sleep(1e-4)
+            srv_lat = srv.wait(tickets[i])
+            lat.append(sub_t[i] - arrival[i] + srv_lat)
+        th.join()
+        wall = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        return wall, lat, st
+
+    burst = [0.0] * R
+    wp, lp = run_plain(burst)
+    ws, lsv, st_b = run_served(burst)
+    same_b = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(work, ref))
+    mu = R / wp                                # plain requests per second
+    lam = 0.8 * mu
+    arrival = list(np.asarray(spec.arrival_s[:R]) * (1000.0 / lam))   # spec drawn at 1000 req/s
+    arrival = [a - arrival[0] for a in arrival]
+    wp2, lp2 = run_plain(arrival)
+    ws2, ls2, st_p = run_served(arrival)
+    same_p = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(work, ref))
+    if not (same_b and same_p):
+        raise SystemExit("served and plain results differ")
+    line = {
+        "metric": METRIC, "value": total / ws, "unit": "keys/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": ws * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+u64", "data": "synthetic (seeded generator; no dataset)",
+        "config": {"workload": "served_%d_requests" % R, "keys": total, "budget_gb": args.budget_gb,
+                   "max_inflight": args.inflight},
+        "burst": {"served_keys_per_s": total / ws, "plain_keys_per_s": total / wp,
+                  "served_p50_s": pct(lsv, 50), "served_p99_s": pct(lsv, 99),
+                  "plain_p50_s": pct(lp, 50), "plain_p99_s": pct(lp, 99), "batches": st_b["batches"],
+                  "peak_admitted_bytes": st_b["peak_bytes"]},
+        "poisson": {"rate_per_s": lam, "plain_rate_per_s": mu,
+                    "served_keys_per_s": total / ws2, "plain_keys_per_s": total / wp2,
+                    "served_p50_s": pct(ls2, 50), "served_p99_s": pct(ls2, 99),
+                    "plain_p50_s": pct(lp2, 50), "plain_p99_s": pct(lp2, 99), "batches": st_p["batches"]},
+        "identical_to_plain": True,
+    }
+    print(json.dumps(line), flush=True)
+    S.close()
+
+
 KERNEL_CLASS_OF = (("k_train", "train"), ("k_hist", "hist"), ("k_scan", "scan"), ("k_classify", "classify"),
                    ("k_layout", "classify"), ("k_round_init", "classify"), ("k_scatter", "scatter"),
                    ("k_base", "base"), ("k_fill", "fill"), ("k_touchup", "touchup"))
@@ -183,6 +400,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verify", action="store_true", help="check the sorted output against numpy")
+    ap.add_argument("--segments", type=int, default=10_000, help="arrays of the segments workload")
+    ap.add_argument("--requests", type=int, default=400, help="requests of the served workload")
+    ap.add_argument("--budget-gb", type=int, default=200)
+    ap.add_argument("--inflight", type=int, default=2)
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_profiles(args)
@@ -196,6 +417,11 @@ def main():
 
     import torch
     import paper_2107_03290_amd as ls
+
+    if args.workload == "segments":
+        return bench_segments(args, torch, ls)
+    if args.workload == "served":
+        return bench_served(args, torch, ls)
 
     t_gen = time.perf_counter()
     keys, wname, n = make_workload(args.workload, args.n)
@@ -246,15 +472,6 @@ def main():
     value = n * K / (gpu_ms / 1e3)
 
     prof = S.profile()
-    dom = max(("hist", "scatter", "base", "fill", "train"), key=lambda k: prof[k][0])
-    ms, launches, byt = prof[dom]
-    achieved = (byt / launches) / ((ms / launches) / 1e3) / 1e9 if launches else 0.0
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (dom, wname))
-    if os.path.exists(tfile):
-        tj = json.load(open(tfile))
-        if tj.get("kernel_source") == kernel_source_hash():
-            traffic = tj.get("bytes_per_launch")
     line = {
         "metric": METRIC,
         "value": value,
@@ -270,10 +487,7 @@ def main():
         "data": "synthetic (seeded generator; no dataset)",
         "config": {"workload": wname, "n": n, "fanout": p.fanout, "leaves": p.leaves, "tile": p.tile,
                    "base_threshold": p.base_threshold, "sample_rate": p.sample_rate},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": byt / launches if launches else 0.0,
-                     "avg_launch_ms": ms / launches if launches else 0.0},
+        "roofline": roofline(prof, wname),
         "kernel_ms_per_step": {k: prof[k][0] / K for k in prof},
         "kernel_GBps": {k: (prof[k][2] / (prof[k][0] / 1e3) / 1e9 if prof[k][0] else 0.0) for k in prof},
         "pipeline": stats[-1],

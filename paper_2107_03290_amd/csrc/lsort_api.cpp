@@ -371,8 +371,8 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
             t.shift = 64 - lf;
         } else {
             t.kind = kGlobal;
-            t.fanout = P.fanout;
-            t.scale = (double)P.fanout;
+            t.fanout = child_fanout(a.n, P.base, P.fanout);
+            t.scale = (double)t.fanout;
             t.leaves = P.leaves;
             t.model = tr.add(a.keys, a.n, sample_size(a.n, P.rate, P.cap), P.seed, P.leaves, a.dtype);
         }
@@ -431,18 +431,32 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         TRY(ensure(C, C->bstat, (uint64_t)R.buckets * 16, st));
         TRY(ensure(C, C->skip, R.buckets, st));
         TRY(ensure(C, C->tflags, (size_t)nt * 4, st));
-        TRY(ensure(C, C->next, (size_t)R.buckets * sizeof(Task), st));
+        // Output lists, sized by what classify can emit: a next-round task
+        // is a bucket of more than T keys; a fill bucket holds at least
+        // max(T/8, 2) keys (plus one piece per kFillPiece keys); a group of
+        // class c > 0 holds more than the previous class cap; a group of
+        // class 0 starts after an empty-free run of small buckets is broken
+        // by the task start, a T-key window boundary or a big / fill bucket,
+        // so there are at most 2 n/T + n/fill_min + 2 of them per task.
+        const uint64_t T1 = (uint64_t)P.base + 1;
+        const uint64_t max_tasks = std::min<uint64_t>(R.buckets, R.nkeys / T1) + 1;
+        const uint64_t fill_min = std::max<uint64_t>(P.base / 8, 2);
+        const uint64_t max_fills = std::min<uint64_t>(R.buckets, R.nkeys / fill_min) + R.nkeys / kFillPiece + 1;
+        const uint64_t g0 = 2 * (R.nkeys / P.base) + R.nkeys / fill_min + 2 * (uint64_t)nt + 2;
+        const uint64_t max_groups[kGroupClasses] = {std::min<uint64_t>(R.buckets, g0) + 1,
+                                                    R.nkeys / (kGroupClassCap[0] + 1) + 1,
+                                                    R.nkeys / (kGroupClassCap[1] + 1) + 1};
+        TRY(ensure(C, C->next, max_tasks * sizeof(Task), st));
         GroupLists gl;
         for (uint32_t c = 0; c < kGroupClasses; ++c) {
-            TRY(ensure(C, C->groups[c], ((size_t)R.ngroups[c] + R.buckets) * sizeof(Group), st,
+            TRY(ensure(C, C->groups[c], ((size_t)R.ngroups[c] + max_groups[c]) * sizeof(Group), st,
                        (size_t)R.ngroups[c] * sizeof(Group)));
             gl.g[c] = (Group*)C->groups[c].p;
         }
-        TRY(ensure(C, C->fills, ((size_t)R.nfill + R.buckets + R.nkeys / kFillPiece + 1) * sizeof(Fill), st,
-                   (size_t)R.nfill * sizeof(Fill)));
+        TRY(ensure(C, C->fills, ((size_t)R.nfill + max_fills) * sizeof(Fill), st, (size_t)R.nfill * sizeof(Fill)));
         // local models of this round's tasks (jobs written by the last layout)
         TRY(train(C, C->ljobs, R.njobs, R.blocks, R.samples, R.leafs, global_models, R.models, st, &prof));
-        TRY(ensure(C, C->ljobs, (size_t)R.buckets * sizeof(ModelJob), st));
+        TRY(ensure(C, C->ljobs, max_tasks * sizeof(ModelJob), st));
         HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, R.buckets, (RoundCtl*)C->ctl.p, st));
         prof.begin(1);
         HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,

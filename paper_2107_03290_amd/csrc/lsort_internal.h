@@ -45,7 +45,7 @@ struct Task {
     uint32_t level;
     uint32_t chunk0;      // first chunk of this task in the round
     uint32_t nchunks;
-    uint32_t bucket_off;  // first bucket of this task in the round's bucket table
+    uint64_t bucket_off;  // first bucket of this task in the round's bucket table
     uint64_t cnt_off;     // first entry of this task in the round's count matrix
     uint64_t cnt_base;    // sum of the sizes of the round's earlier tasks
     uint32_t seg;
@@ -120,7 +120,8 @@ struct RoundCtl {
     uint64_t nkeys;                   // keys in the round's tasks
     uint64_t entries;                 // count-matrix entries
     uint64_t samples, leafs, models;  // training-table sizes
-    uint32_t chunks, buckets, njobs, blocks;
+    uint64_t buckets;
+    uint32_t chunks, njobs, blocks;
     uint32_t max_fanout, max_leaves, max_level;
     uint32_t classified;              // classify workgroups finished (reset every round)
 };
@@ -130,11 +131,30 @@ __host__ __device__ inline size_t model_doubles(uint32_t L) { return 4 + 4 * (si
 // LDS bytes of a model in a partition kernel: L + 1 segments and L indices.
 __host__ __device__ inline size_t model_lds_bytes(uint32_t L) { return (size_t)(L + 1) * 32 + (size_t)L * 2 + 32; }
 
+__host__ __device__ inline uint32_t pow2_at_least(uint64_t x)
+{
+    uint32_t p = 1;
+    while (p < x && p < (1u << 30))
+        p <<= 1;
+    return p;
+}
+
+// Fanout of a range of n keys: many more buckets than needed to bring it
+// under the base threshold (duplicate-heavy ranges need narrow buckets for
+// their repeated keys to end up alone), at least 64, capped by the caller's
+// fanout.  Bounds a round's bucket count by 256 * keys / thresh.
+__host__ __device__ inline uint32_t child_fanout(uint64_t n, uint32_t thresh, uint32_t cap)
+{
+    uint32_t f = pow2_at_least((64u * n + thresh - 1) / thresh);
+    f = f < 64u ? 64u : f;
+    return f > cap ? cap : f;
+}
+
 // Kernel launchers.
 hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks,
                         uint64_t* d_sample, uint64_t* d_minmax, uint32_t* d_lcnt, uint64_t* d_lmin,
                         double* d_models, hipStream_t st);
-hipError_t launch_round_init(uint64_t* d_bstat, uint32_t nbuckets, RoundCtl* d_ctl, hipStream_t st);
+hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, hipStream_t st);
 hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                        const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint32_t max_fanout,
                        uint32_t max_leaves, uint32_t flags, hipStream_t st);

@@ -16,9 +16,9 @@ __device__ __forceinline__ uint32_t find_task(const Task* tasks, uint32_t ntasks
     return lo;
 }
 
-__global__ void k_round_init(uint64_t* bstat, uint32_t nbuckets, RoundCtl* ctl)
+__global__ void k_round_init(uint64_t* bstat, uint64_t nbuckets, RoundCtl* ctl)
 {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         ctl->ntasks = 0;
         ctl->classified = 0;
@@ -29,9 +29,9 @@ __global__ void k_round_init(uint64_t* bstat, uint32_t nbuckets, RoundCtl* ctl)
     }
 }
 
-hipError_t launch_round_init(uint64_t* d_bstat, uint32_t nbuckets, RoundCtl* d_ctl, hipStream_t st)
+hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, hipStream_t st)
 {
-    k_round_init<<<(nbuckets + 255) / 256 + 1, 256, 0, st>>>(d_bstat, nbuckets, d_ctl);
+    k_round_init<<<(uint32_t)((nbuckets + 255) / 256 + 1), 256, 0, st>>>(d_bstat, nbuckets, d_ctl);
     return hipGetLastError();
 }
 
@@ -195,24 +195,6 @@ enum : uint8_t { kEmpty = 0, kSmall = 1, kFillB = 2, kBig = 3, kLead = 0x80 };
 
 constexpr int32_t kNone = 0x7fffffff;
 
-__device__ __forceinline__ uint32_t pow2_at_least(uint64_t x)
-{
-    uint32_t p = 1;
-    while (p < x && p < (1u << 30))
-        p <<= 1;
-    return p;
-}
-
-// Fanout of a child range of n keys: many more buckets than needed to bring
-// it under the base threshold (duplicate-heavy ranges need narrow buckets for
-// their repeated keys to end up alone), capped by the caller's fanout.
-__device__ __forceinline__ uint32_t child_fanout(uint64_t n, uint32_t thresh, uint32_t cap)
-{
-    uint32_t f = pow2_at_least((64u * n + thresh - 1) / thresh);
-    f = f < 64u ? 64u : f;
-    return f > cap ? cap : f;
-}
-
 // ---------------------------------------------------------------- layout --
 
 // Lay out the next round on the device (any block size, multiple of 64 up to
@@ -319,7 +301,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
         if (valid) {
             T.chunk0 = (uint32_t)off[0];
             T.nchunks = (uint32_t)nch;
-            T.bucket_off = (uint32_t)off[1];
+            T.bucket_off = off[1];
             T.cnt_off = off[2];
             T.cnt_base = off[3];
             if (local) {
@@ -350,7 +332,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
         ctl->chunk = chunk;
         ctl->nkeys = nkeys;
         ctl->chunks = (uint32_t)carry[0];
-        ctl->buckets = (uint32_t)carry[1];
+        ctl->buckets = carry[1];
         ctl->entries = carry[2];
         ctl->njobs = (uint32_t)carry[4];
         ctl->samples = carry[5];
