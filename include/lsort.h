@@ -67,7 +67,9 @@ typedef struct {
     uint32_t base_threshold;   /* buckets of at most this many keys are sorted in LDS, in groups of < 2x (default 4096, max 4096) */
     uint32_t flags;            /* LS_FLAG_* */
     double   sample_rate;      /* model training sample (default 0.01) */
-    uint64_t sample_cap;       /* upper bound on one model's sample, 0 = none */
+    uint64_t sample_cap;       /* upper bound on one model's sample (ls_default_params: 262144, so the
+                                  1% rate holds up to 26.2M keys); 0 = none.  A NULL ls_params
+                                  uses the default. */
     uint64_t seed;             /* seed of the counter-based sampler */
 } ls_params;
 
@@ -166,10 +168,13 @@ const char* ls_last_error(ls_ctx* ctx);
 
 /* ---- stage hooks for parity checks against a reference implementation ---- */
 
-/* Train the global model on the 1% sample of d_keys[0..n) (Sec. 6.1) and
- * copy it to h_model_out (HOST, cap doubles) in the layout
- * [xmin, xmax, rs, m'] + per leaf [X_k, y_k, yhi_k, s_k] (4 + 4L doubles;
- * an empty leaf has X_k = +inf).  Synchronous. */
+/* Train the global model on the sample of d_keys[0..n) (Sec. 6.1: a 1%
+ * sample, two layers) and copy it to h_model_out (HOST, cap doubles) in the
+ * layout [xmin, xmax, rs, m'] + for each of the L leaf knots and then the
+ * start knot (at the sample minimum) [X, y, ym, y1, ylo, yhi, s]: the knot,
+ * the sample eCDF below it, at it (mid-rank) and at-or-below it, and the
+ * segment above it (from ylo with slope s, up to yhi); a leaf with no sample
+ * value has X = +inf.  4 + 7 (L + 1) doubles.  Synchronous. */
 ls_status ls_model_train(ls_ctx* ctx, ls_dtype dtype, const void* d_keys, size_t n,
                          const ls_params* p, double* h_model_out, size_t cap);
 

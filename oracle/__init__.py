@@ -154,7 +154,7 @@ def train(keys: np.ndarray, **kw) -> tuple[np.ndarray, np.ndarray]:
     w, dt = as_words(keys)
     p = params(dt, **kw)
     m = lib().orc_sample_size(w.size, p.sample_rate, p.sample_cap)
-    model = np.zeros(4 + 4 * p.leaves, dtype=np.float64)
+    model = np.zeros(4 + 7 * (p.leaves + 1), dtype=np.float64)
     idx = np.zeros(m, dtype=np.uint64)
     rc = lib().orc_train(_u64(w), w.size, ctypes.byref(p), _f64(model), _u64(idx))
     if rc != 0:
@@ -165,7 +165,7 @@ def train(keys: np.ndarray, **kw) -> tuple[np.ndarray, np.ndarray]:
 def train_sample(sample: np.ndarray, leaves: int) -> np.ndarray:
     """Model trained on exactly these sample keys (no sampling step)."""
     w, dt = as_words(sample)
-    model = np.zeros(4 + 4 * leaves, dtype=np.float64)
+    model = np.zeros(4 + 7 * (leaves + 1), dtype=np.float64)
     rc = lib().orc_train_sample(_u64(w), w.size, leaves, dt, _f64(model))
     if rc != 0:
         raise RuntimeError("oracle train failed: %d" % rc)

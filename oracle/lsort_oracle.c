@@ -20,10 +20,13 @@
  *          walking the sub-bucket backwards.
  *   R11/12 histogram of n' slots, reused buffers.
  *   R13    the touch-up insertion sort covers the whole array, ord order.
- *   R14    model: two-layer linear spline (root linear over the sample range,
- *          leaf k knotted at its sample minimum with the exact eCDF value;
- *          a key uses the segment of the largest knot not above it).
- *   R15    eCDF of a duplicated key is its lower rank.
+ *   R14    model: two-layer linear spline over the sorted sample (root linear
+ *          in the totalOrder word; leaf k knotted at its most repeated
+ *          sample value; a start knot at the sample minimum; the sample
+ *          eCDF exact just below, at (mid-rank) and just above each knot; a
+ *          key uses the segment of the largest knot not above it).
+ *   R15    every copy of a key gets the same prediction: its mid-rank in the
+ *          sample when it is a knot.
  *   R16    sample with replacement, m = max(1, ceil(rate*n)).
  *   R17    n <= 1: nothing; n <= small_n: insertion sort.
  *   R18    optional recursion (s_max > 0) into over-full sub-buckets with a
@@ -105,44 +108,76 @@ uint64_t orc_sample_size(uint64_t n, double rate, uint64_t cap)
 
 /* ----------------------------------------------------------------- model -- */
 
+/* Reading R14.  A two-layer model of the sample eCDF:
+ *  - root: leaf = floor((r(x) - r(xmin)) * L / (r(xmax) - r(xmin))), clamped
+ *    to [0, L), where r(x) is the totalOrder word of the double x read as a
+ *    number (log-like spacing: every binade gets leaves, so skewed data
+ *    still spreads over them);
+ *  - leaf k: one spline knot X_k: the value with the most copies among the
+ *    sample values falling into leaf k (ties: the smallest) when it holds at
+ *    least 2 copies and at least 1/L of the sample, else the leaf's smallest
+ *    value; with the exact sample eCDF just below it (y), at it (mid-rank ym)
+ *    and at or below it (y1);
+ *  - a start knot at the sample minimum (index L);
+ *  - between a knot with B sample values below it and d copies and the next
+ *    knot (B' below it), linear from ylo = (B + d - 1/2)/m' to
+ *    (B' + 1/2)/m' (mid-ranks of the last copy and of the next first copy),
+ *    or to (xmax, 1) after the last knot.
+ * A key uses the largest knot not above it: ym at the knot, the segment
+ * above it otherwise, 0 below the sample minimum. */
 typedef struct {
-    double xmin, xmax, rs;
+    double xmin, xmax, rs, r0;
     uint64_t mfin;       /* m': finite sample values */
     uint32_t L;
-    double *X, *y, *yhi, *s;
+    /* L + 1 knots (leaves, then the start knot): X, y, ym, y1, ylo, yhi, s;
+     * ye: where the segment arriving at the knot ends (training only) */
+    double *X, *y, *ym, *y1, *ylo, *yhi, *s, *ye;
 } model_t;
 
 static void model_free(model_t* M)
 {
     free(M->X);
-    M->X = M->y = M->yhi = M->s = NULL;
+    M->X = M->y = M->ym = M->y1 = M->ylo = M->yhi = M->s = M->ye = NULL;
 }
 
 static int model_alloc(model_t* M, uint32_t L)
 {
     memset(M, 0, sizeof *M);
     M->L = L;
-    M->X = (double*)calloc(4u * (size_t)L, sizeof(double));
+    size_t K = (size_t)L + 1;
+    M->X = (double*)calloc(8u * K, sizeof(double));
     if (!M->X)
         return ORC_ERR_NOMEM;
-    M->y = M->X + L;
-    M->yhi = M->y + L;
-    M->s = M->yhi + L;
+    M->y = M->X + K;
+    M->ym = M->y + K;
+    M->y1 = M->ym + K;
+    M->ylo = M->y1 + K;
+    M->yhi = M->ylo + K;
+    M->s = M->yhi + K;
+    M->ye = M->s + K;
     return ORC_OK;
+}
+
+/* Root coordinate: the totalOrder word of a double, read as a number. */
+static double root_coord(double x)
+{
+    uint64_t b;
+    memcpy(&b, &x, sizeof b);
+    return (double)f64_bits_to_ord(b);
 }
 
 /* Root model: which leaf a finite value belongs to. */
 static uint32_t model_leaf(const model_t* M, double x)
 {
-    double t = (x - M->xmin) * M->rs;
-    if (!(t >= 1.0))                 /* also catches NaN (inf * 0) */
+    double t = (root_coord(x) - M->r0) * M->rs;
+    if (!(t >= 1.0))
         return 0;
     if (t >= (double)(M->L - 1u))
         return M->L - 1u;
     return (uint32_t)t;
 }
 
-/* Largest non-empty leaf j < k, or L if there is none. */
+/* Largest non-empty leaf j < k, or L (the start knot) if there is none. */
 static uint32_t model_prev(const model_t* M, uint32_t k)
 {
     while (k-- > 0)
@@ -151,103 +186,163 @@ static uint32_t model_prev(const model_t* M, uint32_t k)
     return M->L;
 }
 
-/* F_A(x): estimated fraction of keys smaller than x (P. 2: the model returns
- * the count of keys less than x, scaled).  The segment used is the one that
- * starts at the largest knot X_j <= x; below the first knot F = 0.  Clamping
- * each segment to [y_j, yhi_j] makes F monotone non-decreasing in x. */
+/* F_A(x): estimated fraction of keys smaller than x (Sec. 2: the model
+ * returns the count of keys less than x, scaled).  Monotone non-decreasing:
+ * knots increase with the leaf index, and each segment is clamped to
+ * [ylo_j, yhi_j] with ylo_j >= ym_j and yhi_j <= the next knot's ym. */
 static double model_F(const model_t* M, double x)
 {
     if (isnan(x) || isinf(x))
         return signbit(x) ? 0.0 : 1.0;
     uint32_t k = model_leaf(M, x);
     uint32_t j = (x >= M->X[k]) ? k : model_prev(M, k);
-    if (j == M->L)
+    if (j == M->L && !(x >= M->X[j]))
         return 0.0;
+    if (x == M->X[j])
+        return M->ym[j];
     if (M->s[j] == 0.0)
-        return M->y[j];
-    double F = fma(x - M->X[j], M->s[j], M->y[j]);
-    if (F < M->y[j])
-        F = M->y[j];
+        return M->ylo[j];
+    double F = fma(x - M->X[j], M->s[j], M->ylo[j]);
+    if (F < M->ylo[j])
+        F = M->ylo[j];
     if (F > M->yhi[j])
         F = M->yhi[j];
     return F;
 }
 
-/* Train the two-layer linear-spline model on sample values given as ord keys
- * (reading R14).  Order-independent: counts and minima only. */
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : (x > y);
+}
+
+/* The values of one knot: B sample values below it, d copies of it. */
+static void set_knot(model_t* M, uint32_t k, double X, uint64_t B, uint64_t d)
+{
+    const double m2 = (double)(2 * M->mfin);
+    M->X[k] = X;
+    M->y[k] = (double)B / (double)M->mfin;
+    M->ym[k] = (double)(2 * B + d) / m2;
+    M->y1[k] = (double)(B + d) / (double)M->mfin;
+    M->ylo[k] = (double)(2 * (B + d) - 1) / m2;
+    M->ye[k] = (double)(2 * B + 1) / m2;
+}
+
+/* Train on sample values given as ord words (order-independent: the sample
+ * is sorted first). */
 static int model_train(model_t* M, const uint64_t* sample, uint64_t m, uint32_t L, uint32_t dtype)
 {
     int rc = model_alloc(M, L);
     if (rc)
         return rc;
-    uint64_t lo = ~0ull, hi = 0;
-    uint64_t mfin = 0;
-    for (uint64_t t = 0; t < m; ++t) {
-        double v = ord_value(sample[t], dtype);
-        if (isnan(v) || isinf(v))
-            continue;
-        ++mfin;
-        if (sample[t] < lo) lo = sample[t];
-        if (sample[t] > hi) hi = sample[t];
-    }
-    M->mfin = mfin;
-    if (mfin == 0) {                 /* no knot at all: every F = 0 */
-        for (uint32_t k = 0; k < L; ++k)
-            M->X[k] = INFINITY;
-        return ORC_OK;
-    }
-    M->xmin = ord_value(lo, dtype);
-    M->xmax = ord_value(hi, dtype);
-    M->rs = (M->xmax > M->xmin) ? (double)L / (M->xmax - M->xmin) : 0.0;
-
-    uint64_t* cnt = (uint64_t*)calloc(L, sizeof(uint64_t));
-    uint64_t* lmin = (uint64_t*)malloc((size_t)L * sizeof(uint64_t));
-    if (!cnt || !lmin) {
-        free(cnt);
-        free(lmin);
+    uint64_t* v = (uint64_t*)malloc((size_t)(m ? m : 1) * sizeof(uint64_t));
+    uint64_t* best = (uint64_t*)calloc((size_t)L, sizeof(uint64_t));   /* per leaf: longest run */
+    uint64_t* bstart = (uint64_t*)calloc((size_t)L, sizeof(uint64_t));
+    uint64_t* first = (uint64_t*)malloc((size_t)L * sizeof(uint64_t)); /* per leaf: first sample index */
+    uint64_t* flen = (uint64_t*)calloc((size_t)L, sizeof(uint64_t));  /* and the length of its run */
+    if (!v || !best || !bstart || !first || !flen) {
+        free(v);
+        free(best);
+        free(bstart);
+        free(first);
+        free(flen);
         model_free(M);
         return ORC_ERR_NOMEM;
     }
-    for (uint32_t k = 0; k < L; ++k)
-        lmin[k] = ~0ull;
+    uint64_t mfin = 0;
     for (uint64_t t = 0; t < m; ++t) {
-        double v = ord_value(sample[t], dtype);
-        if (isnan(v) || isinf(v))
-            continue;
-        uint32_t k = model_leaf(M, v);
-        cnt[k] += 1;
-        if (sample[t] < lmin[k]) lmin[k] = sample[t];
+        double x = ord_value(sample[t], dtype);
+        if (!isnan(x) && !isinf(x))
+            v[mfin++] = sample[t];
     }
-    /* knot of leaf k: (X_k, y_k) with y_k = (sample keys below X_k) / m';
-     * an empty leaf has no knot (X_k = +inf, constant segment). */
-    uint64_t below = 0;
+    M->mfin = mfin;
+    for (uint32_t k = 0; k <= L; ++k)
+        M->X[k] = INFINITY;
+    if (mfin == 0) {                 /* no knot at all: every F = 0 */
+        free(v);
+        free(best);
+        free(bstart);
+        free(first);
+        free(flen);
+        return ORC_OK;
+    }
+    qsort(v, (size_t)mfin, sizeof(uint64_t), cmp_u64);
+    M->xmin = ord_value(v[0], dtype);
+    M->xmax = ord_value(v[mfin - 1], dtype);
+    M->r0 = root_coord(M->xmin);
+    double r1 = root_coord(M->xmax);
+    M->rs = (r1 > M->r0) ? (double)L / (r1 - M->r0) : 0.0;
+    for (uint32_t k = 0; k < L; ++k)
+        first[k] = mfin;
+    /* runs of equal values (as doubles; a run starts at its smallest word) */
+    uint64_t run0_len = 0;
+    for (uint64_t a = 0; a < mfin;) {
+        double x = ord_value(v[a], dtype);
+        uint64_t e = a + 1;
+        while (e < mfin && ord_value(v[e], dtype) == x)
+            ++e;
+        uint32_t k = model_leaf(M, x);
+        if (first[k] == mfin) {
+            first[k] = a;
+            flen[k] = e - a;
+        }
+        if (e - a > best[k]) {
+            best[k] = e - a;
+            bstart[k] = a;
+        }
+        if (a == 0)
+            run0_len = e;
+        a = e;
+    }
+    /* leaf knots; an empty leaf has none (X = +inf, constant at the count
+     * of the sample below the leaf) */
     for (uint32_t k = 0; k < L; ++k) {
-        M->y[k] = (double)below / (double)mfin;
-        M->X[k] = cnt[k] ? ord_value(lmin[k], dtype) : INFINITY;
-        M->yhi[k] = M->y[k];
+        if (best[k] >= 2 && best[k] * L >= mfin) {
+            set_knot(M, k, ord_value(v[bstart[k]], dtype), bstart[k], best[k]);
+        } else if (best[k]) {
+            set_knot(M, k, ord_value(v[first[k]], dtype), first[k], flen[k]);
+        } else {
+            /* samples in earlier leaves = first sample index of the next
+             * non-empty leaf, or all of them */
+            uint64_t nb = mfin;
+            for (uint32_t j = k + 1; j < L; ++j)
+                if (first[j] != mfin) {
+                    nb = first[j];
+                    break;
+                }
+            M->X[k] = INFINITY;
+            M->y[k] = M->ym[k] = M->y1[k] = M->ylo[k] = (double)nb / (double)mfin;
+        }
+        M->yhi[k] = M->ylo[k];
         M->s[k] = 0.0;
-        below += cnt[k];
     }
-    /* segment from each knot to the next knot, or to (xmax, 1) */
-    for (uint32_t k = 0; k < L; ++k) {
-        if (!cnt[k])
+    set_knot(M, L, M->xmin, 0, run0_len);
+    M->yhi[L] = M->ylo[L];
+    M->s[L] = 0.0;
+    /* segment from just above each knot (leaves, then the start knot) to
+     * the next knot, or to (xmax, 1) */
+    for (uint32_t k = 0; k <= L; ++k) {
+        if (isinf(M->X[k]))
             continue;
         double Xh = M->xmax, yh = 1.0;
-        for (uint32_t j = k + 1; j < L; ++j) {
-            if (cnt[j]) {
+        for (uint32_t j = (k == L ? 0 : k + 1); j < L; ++j) {
+            if (!isinf(M->X[j])) {
                 Xh = M->X[j];
-                yh = M->y[j];
+                yh = M->ye[j];
                 break;
             }
         }
-        double sl = (yh - M->y[k]) / (Xh - M->X[k]);
+        double sl = (yh - M->ylo[k]) / (Xh - M->X[k]);
         if (!(sl > 0.0) || isinf(sl))
             sl = 0.0;
         M->yhi[k] = yh;
         M->s[k] = sl;
     }
-    free(cnt);
-    free(lmin);
+    free(v);
+    free(best);
+    free(bstart);
+    free(first);
+    free(flen);
     return ORC_OK;
 }
 
@@ -257,11 +352,15 @@ static void model_export(const model_t* M, double* out)
     out[1] = M->xmax;
     out[2] = M->rs;
     out[3] = (double)M->mfin;
-    for (uint32_t k = 0; k < M->L; ++k) {
-        out[4 + 4 * (size_t)k + 0] = M->X[k];
-        out[4 + 4 * (size_t)k + 1] = M->y[k];
-        out[4 + 4 * (size_t)k + 2] = M->yhi[k];
-        out[4 + 4 * (size_t)k + 3] = M->s[k];
+    for (uint32_t k = 0; k <= M->L; ++k) {
+        double* o = out + 4 + 7 * (size_t)k;
+        o[0] = M->X[k];
+        o[1] = M->y[k];
+        o[2] = M->ym[k];
+        o[3] = M->y1[k];
+        o[4] = M->ylo[k];
+        o[5] = M->yhi[k];
+        o[6] = M->s[k];
     }
 }
 
@@ -274,11 +373,16 @@ static int model_import(model_t* M, const double* in, uint32_t L)
     M->xmax = in[1];
     M->rs = in[2];
     M->mfin = (uint64_t)in[3];
-    for (uint32_t k = 0; k < L; ++k) {
-        M->X[k] = in[4 + 4 * (size_t)k + 0];
-        M->y[k] = in[4 + 4 * (size_t)k + 1];
-        M->yhi[k] = in[4 + 4 * (size_t)k + 2];
-        M->s[k] = in[4 + 4 * (size_t)k + 3];
+    M->r0 = root_coord(M->xmin);
+    for (uint32_t k = 0; k <= L; ++k) {
+        const double* o = in + 4 + 7 * (size_t)k;
+        M->X[k] = o[0];
+        M->y[k] = o[1];
+        M->ym[k] = o[2];
+        M->y1[k] = o[3];
+        M->ylo[k] = o[4];
+        M->yhi[k] = o[5];
+        M->s[k] = o[6];
     }
     return ORC_OK;
 }

@@ -63,9 +63,13 @@ typedef struct {
     int32_t  status;
 } orc_stats;
 
-/* Model export layout (doubles): [xmin, xmax, rs, m'] then, for each leaf k,
- * [X_k, y_k, yhi_k, s_k]; an empty leaf has X_k = +inf.  Size 4 + 4*L. */
-#define ORC_MODEL_DOUBLES(L) (4u + 4u * (uint32_t)(L))
+/* Model export layout (doubles): [xmin, xmax, rs, m'] then, for each of the
+ * L leaf knots and then the start knot (at the sample minimum), [X, y, ym,
+ * y1, ylo, yhi, s]: the knot; the sample eCDF just below it, its mid-rank and
+ * the eCDF at and below it; the segment above the knot (from ylo, slope s,
+ * up to yhi).  A leaf without sample values has X = +inf.
+ * Size 4 + 7*(L+1). */
+#define ORC_MODEL_DOUBLES(L) (4u + 7u * ((uint32_t)(L) + 1u))
 
 void orc_default_params(orc_params* p, uint32_t dtype);
 

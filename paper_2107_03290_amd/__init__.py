@@ -279,7 +279,7 @@ class Sorter:
         import numpy as np
         _check_tensor(t)
         leaves = (p.leaves if p is not None and p.leaves else 1024)
-        out = np.zeros(4 + 4 * leaves, dtype=np.float64)
+        out = np.zeros(4 + 7 * (leaves + 1), dtype=np.float64)
         self._check(lib().ls_model_train(self._ctx, _dtype_code(t), t.data_ptr(), t.numel(), _pp(p),
                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
         return out

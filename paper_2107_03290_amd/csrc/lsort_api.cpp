@@ -28,6 +28,7 @@ constexpr uint32_t kDefaultLeaves = 1024;
 constexpr uint32_t kDefaultTile = 4096;
 constexpr uint32_t kDefaultBase = 4096;
 constexpr uint64_t kDefaultSeed = 0x2107032900000001ull;
+constexpr uint64_t kDefaultSampleCap = 1ull << 18;   // the 1% rate holds up to 26.2M keys
 
 struct DevBuf {
     void* p = nullptr;
@@ -71,7 +72,8 @@ uint32_t group_class(uint32_t n)
 struct ls_ctx {
     int device = 0;
     std::string err;
-    DevBuf scratch, tune, models, sample, minmax, lcnt, lmin, gjobs, ljobs, tasks, next, cnt, pos, scantmp, bstat,
+    DevBuf scratch, tune, ids, models, sample, sample2, tbest, tfirst, gjobs, ljobs, tasks, next, cnt, pos, scantmp,
+        bstat,
         skip, tflags, fills, ctl;
     DevBuf groups[kGroupClasses];
     PinBuf pin_tasks, pin_jobs, pin_groups[kGroupClasses];
@@ -223,7 +225,7 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
     P.base = kDefaultBase;
     P.flags = 0;
     P.rate = 0.01;
-    P.cap = 0;
+    P.cap = kDefaultSampleCap;
     P.seed = kDefaultSeed;
     if (p) {
         if (p->struct_size != sizeof(ls_params))
@@ -247,8 +249,7 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
         return fail(C, LS_ERR_INVALID, "base_threshold must be in [2, 4096]");
     if (!(P.rate > 0.0) || P.rate > 1.0)
         return fail(C, LS_ERR_INVALID, "sample_rate must be in (0, 1]");
-    size_t scatter_lds = (((size_t)P.tile * 10 + (size_t)P.fanout * 16 + 15) & ~(size_t)15) +
-                         model_lds_bytes(P.leaves) + 128;
+    size_t scatter_lds = scatter_lds_bytes(P.tile, P.fanout) + 128;
     size_t hist_lds = (((size_t)P.fanout * 20 + 15) & ~(size_t)15) + model_lds_bytes(P.leaves) + 64;
     if (scatter_lds > C->lds_limit || hist_lds > C->lds_limit)
         return fail(C, LS_ERR_UNSUPPORTED, "tile/fanout/leaves exceed the LDS of one workgroup");
@@ -258,7 +259,7 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
 // Global models of the large arrays, built on the host.
 struct Trainer {
     std::vector<ModelJob> jobs;
-    uint64_t samples = 0, leaves = 0, models = 0;
+    uint64_t samples = 0, leaves = 0, models = 0, max_sample = 0;
     uint32_t blocks = 0;
 
     uint64_t add(const uint64_t* src, uint64_t n, uint64_t m, uint64_t seed, uint32_t L, uint32_t dtype)
@@ -274,7 +275,8 @@ struct Trainer {
         J.leaves = L;
         J.dtype = dtype;
         J.block0 = blocks;
-        J.nblocks = (uint32_t)((m + 2047) / 2048);
+        J.nblocks = (uint32_t)((m + kSampleBlock - 1) / kSampleBlock);
+        max_sample = std::max(max_sample, m);
         samples += m;
         leaves += L;
         models += model_doubles(L);
@@ -286,17 +288,18 @@ struct Trainer {
 
 // Train njobs models described by d_jobs (device) into the pool at model_base.
 ls_status train(ls_ctx* C, const DevBuf& jobs, uint32_t njobs, uint32_t blocks, uint64_t samples, uint64_t leafs,
-                uint64_t model_base, uint64_t models, hipStream_t st, Prof* prof)
+                uint64_t max_sample, uint64_t model_base, uint64_t models, hipStream_t st, Prof* prof)
 {
     if (!njobs)
         return LS_OK;
     TRY(ensure(C, C->models, (model_base + models) * sizeof(double), st, model_base * sizeof(double)));
     TRY(ensure(C, C->sample, samples * 8, st));
-    // the statistics tables start neutral (zero) and the fit kernel leaves
-    // them neutral; only freshly allocated memory needs clearing
-    DevBuf* tabs[3] = {&C->minmax, &C->lcnt, &C->lmin};
-    const size_t need[3] = {(size_t)njobs * 16, leafs * 4, leafs * 8};
-    for (int i = 0; i < 3; ++i) {
+    TRY(ensure(C, C->sample2, samples * 8, st));
+    // the per-leaf tables start at zero and the fit kernel leaves them at
+    // zero; only freshly allocated memory needs clearing
+    DevBuf* tabs[2] = {&C->tbest, &C->tfirst};
+    const size_t need[2] = {leafs * 8, leafs * 8};
+    for (int i = 0; i < 2; ++i) {
         const void* before = tabs[i]->p;
         TRY(ensure(C, *tabs[i], need[i], st));
         if (tabs[i]->p != before)
@@ -304,8 +307,9 @@ ls_status train(ls_ctx* C, const DevBuf& jobs, uint32_t njobs, uint32_t blocks, 
     }
     if (prof)
         prof->begin(0);
-    HIPCHECK(C, launch_train((const ModelJob*)jobs.p, njobs, blocks, (uint64_t*)C->sample.p, (uint64_t*)C->minmax.p,
-                             (uint32_t*)C->lcnt.p, (uint64_t*)C->lmin.p, (double*)C->models.p, st));
+    HIPCHECK(C, launch_train((const ModelJob*)jobs.p, njobs, blocks, max_sample, (uint64_t*)C->sample.p,
+                             (uint64_t*)C->sample2.p, (uint64_t*)C->tbest.p, (uint64_t*)C->tfirst.p,
+                             (double*)C->models.p, st));
     if (prof)
         prof->end((double)samples * 16.0);
     return LS_OK;
@@ -395,7 +399,8 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
     if (!tr.jobs.empty()) {
         TRY(ensure(C, C->gjobs, tr.jobs.size() * sizeof(ModelJob), st));
         TRY(upload(C, C->pin_jobs, C->gjobs, tr.jobs, st));
-        TRY(train(C, C->gjobs, (uint32_t)tr.jobs.size(), tr.blocks, tr.samples, tr.leaves, 0, tr.models, st, &prof));
+        TRY(train(C, C->gjobs, (uint32_t)tr.jobs.size(), tr.blocks, tr.samples, tr.leaves, tr.max_sample, 0,
+                  tr.models, st, &prof));
     }
     LayoutParams lp;
     lp.fanout = P.fanout;
@@ -429,6 +434,7 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         TRY(ensure(C, C->pos, R.entries * 8, st));
         TRY(ensure(C, C->scantmp, scan_tmp_entries(R.entries) * 8, st));
         TRY(ensure(C, C->bstat, (uint64_t)R.buckets * 16, st));
+        TRY(ensure(C, C->ids, R.nkeys * 2, st));
         TRY(ensure(C, C->skip, R.buckets, st));
         TRY(ensure(C, C->tflags, (size_t)nt * 4, st));
         // Output lists, sized by what classify can emit: a next-round task
@@ -455,13 +461,15 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         }
         TRY(ensure(C, C->fills, ((size_t)R.nfill + max_fills) * sizeof(Fill), st, (size_t)R.nfill * sizeof(Fill)));
         // local models of this round's tasks (jobs written by the last layout)
-        TRY(train(C, C->ljobs, R.njobs, R.blocks, R.samples, R.leafs, global_models, R.models, st, &prof));
+        TRY(train(C, C->ljobs, R.njobs, R.blocks, R.samples, R.leafs, R.max_sample, global_models, R.models, st,
+                  &prof));
         TRY(ensure(C, C->ljobs, max_tasks * sizeof(ModelJob), st));
         HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, R.buckets, (RoundCtl*)C->ctl.p, st));
         prof.begin(1);
         HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
-                                (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, R.max_fanout, R.max_leaves, flags, st));
-        prof.end((double)R.nkeys * 8.0);
+                                (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, (uint16_t*)C->ids.p, R.max_fanout,
+                                R.max_leaves, flags, st));
+        prof.end((double)R.nkeys * 10.0);
         prof.begin(2);
         HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, R.entries, (uint64_t*)C->scantmp.p,
                                 st));
@@ -474,16 +482,17 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
                                     st));
         prof.end((double)R.buckets * 32.0);
         prof.begin(4);
-        HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
+        HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const uint16_t*)C->ids.p,
                                    (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
-                                   (const uint32_t*)C->tflags.p, P.tile, R.max_fanout, R.max_leaves, flags, st));
+                                   (const uint32_t*)C->tflags.p, P.tile, R.max_fanout, st));
         prof.end(0.0);
         TRY(wait_ctl(C, st));
         if (prof.on && !prof.recs.empty()) {
-            // scatter: reads every key of a task that progressed, writes those not in all-equal buckets
+            // scatter: reads every key (and its bucket id) of a task that
+            // progressed, writes those not in all-equal buckets
             const double moved = (double)(R.nkeys - (C->h_ctl->stall_keys - R.stall_keys));
             const double kept = moved - (double)(C->h_ctl->fillkeys - R.fillkeys);
-            prof.recs.back().bytes = 8.0 * moved + 8.0 * kept;
+            prof.recs.back().bytes = 10.0 * moved + 8.0 * kept;
         }
         prof.collect();
     }
@@ -568,6 +577,7 @@ void ls_default_params(ls_params* p)
     p->base_threshold = kDefaultBase;
     p->sample_rate = 0.01;
     p->seed = kDefaultSeed;
+    p->sample_cap = kDefaultSampleCap;
 }
 
 ls_status ls_create(ls_ctx** out, int device)
@@ -604,7 +614,7 @@ ls_status ls_destroy(ls_ctx* C)
         return LS_ERR_INVALID;
     (void)hipSetDevice(C->device);
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&C->scratch, &C->tune, &C->models, &C->sample, &C->minmax, &C->lcnt, &C->lmin, &C->gjobs,
+    DevBuf* bufs[] = {&C->scratch, &C->tune, &C->ids, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst, &C->gjobs,
                       &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
                       &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2]};
     for (DevBuf* b : bufs)
@@ -633,7 +643,8 @@ ls_status ls_workspace_size(ls_ctx* C, ls_dtype dtype, size_t n, const ls_params
     size_t chunks = kTargetChunks + 64;
     size_t tables = (size_t)P.fanout * chunks * 12 + (size_t)P.fanout * 64 + model_doubles(P.leaves) * 8 * 4;
     size_t lists = (n / 2 + P.fanout) * (sizeof(Group) + sizeof(Fill)) / 8;
-    *bytes = n * 8 + tables + lists + (n / 50 + 4096) * 8;
+    // scratch keys, bucket ids, round tables, output lists, training sample
+    *bytes = n * 8 + n * 2 + tables + lists + (2 * std::min<size_t>(n / 50 + 4096, kDefaultSampleCap + 4096)) * 8;
     return LS_OK;
 }
 
@@ -883,7 +894,8 @@ ls_status ls_model_train(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n
         return LS_ERR_INVALID;
     Params P;
     TRY(resolve(C, p, P));
-    if (cap < 4 + 4 * (size_t)P.leaves)
+    const uint32_t L = P.leaves;
+    if (cap < 4 + 7 * ((size_t)L + 1))
         return fail(C, LS_ERR_INVALID, "model output buffer too small");
     HIPCHECK(C, hipSetDevice(C->device));
     hipStream_t st = nullptr;
@@ -891,18 +903,22 @@ ls_status ls_model_train(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n
     tr.add((const uint64_t*)d_keys, n, sample_size(n, P.rate, P.cap), P.seed, P.leaves, dtype);
     TRY(ensure(C, C->gjobs, sizeof(ModelJob), st));
     TRY(upload(C, C->pin_jobs, C->gjobs, tr.jobs, st));
-    TRY(train(C, C->gjobs, 1, tr.blocks, tr.samples, tr.leaves, 0, tr.models, st, nullptr));
+    TRY(train(C, C->gjobs, 1, tr.blocks, tr.samples, tr.leaves, tr.max_sample, 0, tr.models, st, nullptr));
     HIPCHECK(C, hipStreamSynchronize(st));
-    std::vector<double> dev(model_doubles(P.leaves));
+    std::vector<double> dev(model_doubles(L));
     HIPCHECK(C, hipMemcpy(dev.data(), C->models.p, dev.size() * 8, hipMemcpyDeviceToHost));
-    const uint32_t L = P.leaves;
     for (int i = 0; i < 4; ++i)
         h_model_out[i] = dev[i];
-    for (uint32_t k = 0; k < L; ++k) {
-        h_model_out[4 + 4 * k + 0] = dev[4 + 4 * k + 0];   // device leaf: {X, y, s, yhi}
-        h_model_out[4 + 4 * k + 1] = dev[4 + 4 * k + 1];
-        h_model_out[4 + 4 * k + 2] = dev[4 + 4 * k + 3];
-        h_model_out[4 + 4 * k + 3] = dev[4 + 4 * k + 2];
+    for (uint32_t k = 0; k <= L; ++k) {
+        double* o = h_model_out + 4 + 7 * (size_t)k;          // export knot: {X, y, ym, y1, ylo, yhi, s}
+        const double* d = dev.data() + kModelSeg + 4 * (size_t)k;   // device knot: {X, ylo, s, yhi}
+        o[0] = d[0];
+        o[1] = dev[model_y_off(L) + k];
+        o[2] = dev[model_ym_off(L) + k];
+        o[3] = dev[model_y1_off(L) + k];
+        o[4] = d[1];
+        o[5] = d[3];
+        o[6] = d[2];
     }
     return LS_OK;
 }
@@ -921,17 +937,23 @@ ls_status ls_stage_hist(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n,
     std::vector<double> dev(model_doubles(leaves), 0.0);
     for (int i = 0; i < 4; ++i)
         dev[i] = h_model[i];
-    uint32_t* prev = reinterpret_cast<uint32_t*>(dev.data() + 4 + 4 * (size_t)leaves);
+    uint32_t* prev = reinterpret_cast<uint32_t*>(dev.data() + model_prev_off(leaves));
     uint32_t last = kNoPrev;
-    for (uint32_t k = 0; k < leaves; ++k) {
-        double X = h_model[4 + 4 * k];
-        dev[4 + 4 * k + 0] = X;                           // export leaf: {X, y, yhi, s}
-        dev[4 + 4 * k + 1] = h_model[4 + 4 * k + 1];
-        dev[4 + 4 * k + 3] = h_model[4 + 4 * k + 2];
-        dev[4 + 4 * k + 2] = h_model[4 + 4 * k + 3];
-        prev[k] = last;
-        if (!std::isinf(X))
-            last = k;
+    for (uint32_t k = 0; k <= leaves; ++k) {
+        const double* o = h_model + 4 + 7 * (size_t)k;        // export knot: {X, y, ym, y1, ylo, yhi, s}
+        double* d = dev.data() + kModelSeg + 4 * (size_t)k;   // device knot: {X, ylo, s, yhi}
+        d[0] = o[0];
+        d[1] = o[4];
+        d[2] = o[6];
+        d[3] = o[5];
+        dev[model_ym_off(leaves) + k] = o[2];
+        dev[model_y_off(leaves) + k] = o[1];
+        dev[model_y1_off(leaves) + k] = o[3];
+        if (k < leaves) {
+            prev[k] = last;
+            if (!std::isinf(o[0]))
+                last = k;
+        }
     }
     TRY(ensure(C, C->models, dev.size() * 8, st));
     TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
@@ -953,8 +975,10 @@ ls_status ls_stage_hist(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n,
     TRY(ensure(C, C->bstat, (size_t)fanout * 16, st));
     HIPCHECK(C, hipMemcpy(C->tasks.p, &t, sizeof(Task), hipMemcpyHostToDevice));
     HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, fanout, (RoundCtl*)C->ctl.p, st));
+    TRY(ensure(C, C->ids, n * 2, st));
     HIPCHECK(C, launch_hist((const Task*)C->tasks.p, 1, t.nchunks, chunk, (const double*)C->models.p,
-                            (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, fanout, leaves, 0, st));
+                            (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, (uint16_t*)C->ids.p, fanout, leaves, 0,
+                            st));
     HIPCHECK(C, hipDeviceSynchronize());
     std::vector<uint32_t> cnt((size_t)fanout * t.nchunks);
     std::vector<uint64_t> bs((size_t)fanout * 2);

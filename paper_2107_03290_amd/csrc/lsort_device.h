@@ -76,10 +76,20 @@ __device__ __forceinline__ uint64_t sample_index(uint64_t seed, uint64_t t, uint
 //   "previous knot" indices (kNoPrev: none).
 // In LDS the segments are double2 pairs {X, y}, {s, yhi}; entry L is a
 // constant-zero segment that stands for "below the first knot".
+// Root coordinate of a value: the totalOrder word of the double, as a number.
+__device__ __forceinline__ double root_coord(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    return __ull2double_rn((b >> 63) ? ~b : (b | kSign));
+}
+
+// A model as partition kernels use it, from LDS.  Knots 0..L-1 are the leaf
+// knots, knot L the start knot at the sample minimum.
 struct SModel {
-    double xmin, rs, lm1;
+    double r0, rs, lm1;
     uint32_t L;
-    const double2* seg;     // 2 * (L + 1) entries
+    const double2* seg;     // 2 (L + 1) entries: {X, ylo}, {s, yhi}
+    const double* ym;       // L + 1 mid-ranks at the knots
     const uint16_t* prev;   // L entries, L for none
 };
 
@@ -88,40 +98,43 @@ __device__ __forceinline__ void load_model(SModel& M, const double* pool, uint64
 {
     const double* g = pool + off;
     double2* seg = reinterpret_cast<double2*>(lds);
-    uint16_t* prev = reinterpret_cast<uint16_t*>(seg + 2 * (L + 1));
-    const double2* gs = reinterpret_cast<const double2*>(g + 4);
-    for (uint32_t i = threadIdx.x; i < 2 * L; i += blockDim.x)
+    double* ym = reinterpret_cast<double*>(seg + 2 * (L + 1));
+    uint16_t* prev = reinterpret_cast<uint16_t*>(ym + (L + 1));
+    const double2* gs = reinterpret_cast<const double2*>(g + kModelSeg);
+    for (uint32_t i = threadIdx.x; i < 2 * (L + 1); i += blockDim.x)
         seg[i] = gs[i];
-    if (threadIdx.x == 0) {
-        seg[2 * L] = make_double2(0.0, 0.0);       // {X, y}: F = y = 0
-        seg[2 * L + 1] = make_double2(0.0, 0.0);   // {s, yhi}: s = 0
-    }
-    const uint32_t* gp = reinterpret_cast<const uint32_t*>(g + 4 + 4 * (size_t)L);
+    const double* gym = g + model_ym_off(L);
+    for (uint32_t i = threadIdx.x; i <= L; i += blockDim.x)
+        ym[i] = gym[i];
+    const uint32_t* gp = reinterpret_cast<const uint32_t*>(g + model_prev_off(L));
     for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
         const uint32_t p = gp[i];
         prev[i] = (uint16_t)(p == kNoPrev ? L : p);
     }
-    M.xmin = g[0];
+    M.r0 = root_coord(g[0]);
     M.rs = g[2];
     M.L = L;
     M.lm1 = (double)(L - 1u);
     M.seg = seg;
+    M.ym = ym;
     M.prev = prev;
 }
 
-// F(x): fraction of the sample below x, interpolated linearly along the
-// segment of the largest knot not above x (knots: leaf minima of the
-// sample); 0 below the first knot; non-finite keys map to 0 or 1 by sign.
+// F(x), the model's estimate of the fraction of keys below x: the segment of
+// the largest knot not above x; the knot's mid-rank at the knot itself; 0
+// below the sample minimum; non-finite keys map to 0 or 1 by sign.
 template <uint32_t DT>
 __device__ __forceinline__ double model_F(const SModel& M, uint64_t raw)
 {
     const double x = key_value(raw, DT);
-    const double t = (x - M.xmin) * M.rs;
+    const double r = DT == kF64 ? __ull2double_rn(to_ord(raw, kF64)) : root_coord(x);
+    const double t = (r - M.r0) * M.rs;
     const uint32_t k = t >= 1.0 ? (t >= M.lm1 ? M.L - 1u : (uint32_t)t) : 0u;
-    double2 a = M.seg[2 * k];         // {X, y}
+    uint32_t j = k;
+    double2 a = M.seg[2 * k];         // {X, ylo}
     double2 b = M.seg[2 * k + 1];     // {s, yhi}
     if (x < a.x) {                    // below this leaf's knot: previous knot
-        const uint32_t j = M.prev[k];
+        j = M.prev[k];
         a = M.seg[2 * j];
         b = M.seg[2 * j + 1];
     }
@@ -129,6 +142,10 @@ __device__ __forceinline__ double model_F(const SModel& M, uint64_t raw)
     F = F < a.y ? a.y : F;
     F = F > b.y ? b.y : F;
     F = b.x == 0.0 ? a.y : F;
+    if (x == a.x)
+        F = M.ym[j];
+    if (j == M.L && !(x >= a.x))      // below the sample minimum
+        F = 0.0;
     if (DT == kF64 && nonfinite(raw, kF64))
         F = (raw & kSign) ? 0.0 : 1.0;
     return F;
@@ -154,6 +171,99 @@ template <uint32_t DT>
 __device__ __forceinline__ uint32_t msd_bucket(uint64_t raw, uint32_t shift, uint32_t fanout)
 {
     return (uint32_t)((to_ord(raw, DT) >> shift) & (uint64_t)(fanout - 1u));
+}
+
+// ------------------------------------------------------- LDS bitonic sort --
+
+// Ascending bitonic network over N = 2^logN (16 <= N <= 16 * NT) words in
+// LDS, stored at base_pad(i).  Each thread keeps 16 elements in registers:
+// the 16 indices that differ only in a window of 4 index bits.  Up to four
+// consecutive stages of the network touch only bits inside one window, so
+// each LDS round trip runs four stages in registers; a phase of the network
+// needs ceil(p/4) round trips.  All NT threads call it; the words must be in
+// LDS and synchronised on entry, and are sorted and synchronised on exit.
+__host__ __device__ __forceinline__ uint32_t base_pad(uint32_t i) { return i + (i >> 4); }
+
+// element index of register m of thread t, the 4 register bits at [lo, lo+4)
+__device__ __forceinline__ uint32_t base_idx(uint32_t t, uint32_t lo, uint32_t m)
+{
+    const uint32_t low = t & ((1u << lo) - 1u);
+    return low | (m << lo) | ((t >> lo) << (lo + 4));
+}
+
+__device__ __forceinline__ void cmpex(uint64_t& a, uint64_t& b, bool up)
+{
+    const bool sw = (a > b) == up;
+    const uint64_t x = sw ? b : a;
+    const uint64_t y = sw ? a : b;
+    a = x;
+    b = y;
+}
+
+// Stages on register bits top..0 (top <= 3) with one direction.
+__device__ __forceinline__ void reg_stages(uint64_t (&r)[16], uint32_t top, bool up)
+{
+#pragma unroll
+    for (int rb = 3; rb >= 0; --rb) {
+        if ((uint32_t)rb <= top) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m)
+                if (!(m & (1 << rb)))
+                    cmpex(r[m], r[m | (1 << rb)], up);
+        }
+    }
+}
+
+template <uint32_t NT>
+__device__ void lds_bitonic(uint64_t* s, uint32_t logN)
+{
+    const uint32_t t = threadIdx.x;
+    const bool act = t < ((1u << logN) >> 4);
+    uint64_t r[16];
+    // phases 1..4: the 16 consecutive elements of each thread
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+            r[m] = s[base_pad(16 * t + m)];
+#pragma unroll
+        for (int p = 1; p <= 4; ++p) {
+#pragma unroll
+            for (int rb = p - 1; rb >= 0; --rb) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    if (!(m & (1 << rb))) {
+                        const uint32_t idx = 16u * t + (uint32_t)m;
+                        const bool up = ((idx >> p) & 1u) == 0 || (uint32_t)p == logN;
+                        cmpex(r[m], r[m | (1 << rb)], up);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+            s[base_pad(16 * t + m)] = r[m];
+    }
+    __syncthreads();
+    // phases 5..logN: stages on bits p-1 .. 0 in windows of four bits
+    for (uint32_t p = 5; p <= logN; ++p) {
+        int32_t bit = (int32_t)p - 1;
+        while (bit >= 0) {
+            const uint32_t lo = bit >= 3 ? (uint32_t)bit - 3 : 0u;
+            if (act) {
+                const uint32_t i0 = base_idx(t, lo, 0);
+                const bool up = p == logN || ((i0 >> p) & 1u) == 0;
+#pragma unroll
+                for (int m = 0; m < 16; ++m)
+                    r[m] = s[base_pad(base_idx(t, lo, (uint32_t)m))];
+                reg_stages(r, (uint32_t)bit - lo, up);
+#pragma unroll
+                for (int m = 0; m < 16; ++m)
+                    s[base_pad(base_idx(t, lo, (uint32_t)m))] = r[m];
+            }
+            __syncthreads();
+            bit = (int32_t)lo - 1;
+        }
+    }
 }
 
 // ------------------------------------------------------------ block scans --

@@ -6,45 +6,10 @@ namespace lsort {
 
 // ------------------------------------------------------------- base case --
 
-// Sort one group (fewer than 2*thresh <= 8192 keys) in LDS with a bitonic
-// network over the next power of two N >= 16, padded with the largest word.
-// Each thread keeps 16 elements in registers: the 16 indices that differ only
-// in a window of 4 index bits.  Up to four consecutive stages of the network
-// touch only bits inside one window, so each LDS round trip runs four stages
-// in registers; a phase of the network needs ceil(p/4) round trips.  Groups
-// come in three size classes so that small groups run in small workgroups:
-// up to 1024 keys on 64 lanes, 4096 on 256, 8192 on 512.
-__host__ __device__ __forceinline__ uint32_t base_pad(uint32_t i) { return i + (i >> 4); }
-
-// element index of register m of thread t, the 4 register bits at [lo, lo+4)
-__device__ __forceinline__ uint32_t base_idx(uint32_t t, uint32_t lo, uint32_t m)
-{
-    const uint32_t low = t & ((1u << lo) - 1u);
-    return low | (m << lo) | ((t >> lo) << (lo + 4));
-}
-
-__device__ __forceinline__ void cmpex(uint64_t& a, uint64_t& b, bool up)
-{
-    const uint64_t lo = a < b ? a : b;
-    const uint64_t hi = a < b ? b : a;
-    a = up ? lo : hi;
-    b = up ? hi : lo;
-}
-
-// Stages on register bits top..0 (top <= 3) with one direction.
-__device__ __forceinline__ void reg_stages(uint64_t (&r)[16], uint32_t top, bool up)
-{
-#pragma unroll
-    for (int rb = 3; rb >= 0; --rb) {
-        if ((uint32_t)rb <= top) {
-#pragma unroll
-            for (int m = 0; m < 16; ++m)
-                if (!(m & (1 << rb)))
-                    cmpex(r[m], r[m | (1 << rb)], up);
-        }
-    }
-}
-
+// Sort one group (fewer than 2*thresh <= 8192 keys) in LDS with the bitonic
+// network of lds_bitonic.  Groups come in three size classes so that small
+// groups run in small workgroups: up to 1024 keys on 64 lanes, 4096 on 256,
+// 8192 on 512.
 template <uint32_t NT>
 __global__ __launch_bounds__(NT) void k_base(const Group* groups)
 {
@@ -58,57 +23,11 @@ __global__ __launch_bounds__(NT) void k_base(const Group* groups)
     while ((1u << logN) < n)
         ++logN;
     const uint32_t N = 1u << logN;
-    const uint32_t t = threadIdx.x;
-    const bool act = t < (N >> 4);
-    for (uint32_t i = t; i < N; i += NT)
+    for (uint32_t i = threadIdx.x; i < N; i += NT)
         s[base_pad(i)] = i < n ? to_ord(G.src[i], G.dtype) : ~0ull;
     __syncthreads();
-    uint64_t r[16];
-    // phases 1..4: the 16 consecutive elements of each thread
-    if (act) {
-#pragma unroll
-        for (int m = 0; m < 16; ++m)
-            r[m] = s[base_pad(16 * t + m)];
-#pragma unroll
-        for (int p = 1; p <= 4; ++p) {
-#pragma unroll
-            for (int rb = p - 1; rb >= 0; --rb) {
-#pragma unroll
-                for (int m = 0; m < 16; ++m) {
-                    if (!(m & (1 << rb))) {
-                        const uint32_t idx = 16u * t + (uint32_t)m;
-                        const bool up = ((idx >> p) & 1u) == 0 || (uint32_t)p == logN;
-                        cmpex(r[m], r[m | (1 << rb)], up);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < 16; ++m)
-            s[base_pad(16 * t + m)] = r[m];
-    }
-    __syncthreads();
-    // phases 5..logN: stages on bits p-1 .. 0 in windows of four bits
-    for (uint32_t p = 5; p <= logN; ++p) {
-        int32_t bit = (int32_t)p - 1;
-        while (bit >= 0) {
-            const uint32_t lo = bit >= 3 ? (uint32_t)bit - 3 : 0u;
-            if (act) {
-                const uint32_t i0 = base_idx(t, lo, 0);
-                const bool up = p == logN || ((i0 >> p) & 1u) == 0;
-#pragma unroll
-                for (int m = 0; m < 16; ++m)
-                    r[m] = s[base_pad(base_idx(t, lo, (uint32_t)m))];
-                reg_stages(r, (uint32_t)bit - lo, up);
-#pragma unroll
-                for (int m = 0; m < 16; ++m)
-                    s[base_pad(base_idx(t, lo, (uint32_t)m))] = r[m];
-            }
-            __syncthreads();
-            bit = (int32_t)lo - 1;
-        }
-    }
-    for (uint32_t i = t; i < n; i += NT)
+    lds_bitonic<NT>(s, logN);
+    for (uint32_t i = threadIdx.x; i < n; i += NT)
         G.dst[i] = from_ord(s[base_pad(i)], G.dtype);
 }
 

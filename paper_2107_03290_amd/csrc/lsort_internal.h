@@ -16,6 +16,7 @@ constexpr uint32_t kNoPrev = 0xffffu;      // "no knot below": F = 0
 constexpr uint64_t kFillPiece = 1u << 16;  // keys per fill work item
 constexpr uint32_t kTargetChunks = 2048;   // chunks per partition round (8 per CU)
 constexpr uint32_t kLocalMinSample = 1024; // smallest sample of a local model
+constexpr uint32_t kSampleBlock = 4096;    // sample keys per training block (one LDS-sorted run)
 constexpr uint32_t kGroupClasses = 3;      // base-case size classes: <= 1024, 4096, 8192 keys
 constexpr uint32_t kGroupClassCap[kGroupClasses] = {1024, 4096, 8192};
 
@@ -120,16 +121,39 @@ struct RoundCtl {
     uint64_t nkeys;                   // keys in the round's tasks
     uint64_t entries;                 // count-matrix entries
     uint64_t samples, leafs, models;  // training-table sizes
+    uint64_t max_sample;              // largest sample of one job
     uint64_t buckets;
     uint32_t chunks, njobs, blocks;
     uint32_t max_fanout, max_leaves, max_level;
     uint32_t classified;              // classify workgroups finished (reset every round)
 };
 
-__host__ __device__ inline size_t model_doubles(uint32_t L) { return 4 + 4 * (size_t)L + (L + 1) / 2; }
+// Device model layout (doubles): header [xmin, xmax, rs, m'], then for the
+// L leaf knots and the start knot (index L): {X, ylo, s, yhi} each; then the
+// L + 1 mid-ranks ym, the L + 1 values y and y1 (kept for export only), and L
+// previous-knot indices (u32, kNoPrev for none).
+constexpr uint32_t kModelSeg = 4;
+__host__ __device__ inline size_t model_ym_off(uint32_t L) { return kModelSeg + 4 * ((size_t)L + 1); }
+__host__ __device__ inline size_t model_y_off(uint32_t L) { return model_ym_off(L) + L + 1; }
+__host__ __device__ inline size_t model_y1_off(uint32_t L) { return model_y_off(L) + L + 1; }
+__host__ __device__ inline size_t model_prev_off(uint32_t L) { return model_y1_off(L) + L + 1; }
+// (rounded up to an even count, so consecutive models keep their knot
+// records 16-byte aligned)
+__host__ __device__ inline size_t model_doubles(uint32_t L) { return (model_prev_off(L) + (L + 1) / 2 + 1) & ~(size_t)1; }
 
-// LDS bytes of a model in a partition kernel: L + 1 segments and L indices.
-__host__ __device__ inline size_t model_lds_bytes(uint32_t L) { return (size_t)(L + 1) * 32 + (size_t)L * 2 + 32; }
+// LDS bytes of a model in a partition kernel: L + 1 segments and mid-ranks,
+// L indices.
+__host__ __device__ inline size_t model_lds_bytes(uint32_t L)
+{
+    return (size_t)(L + 1) * 40 + (size_t)L * 2 + 32;
+}
+
+// LDS bytes of the scatter: the staged tile (8 B keys + 2 B ids) and, per
+// bucket, the cursor (8 B), tile count and tile start (4 B each).
+__host__ __device__ inline size_t scatter_lds_bytes(uint32_t tile, uint32_t fanout)
+{
+    return ((size_t)tile * 10 + (size_t)fanout * 16 + 15) & ~(size_t)15;
+}
 
 __host__ __device__ inline uint32_t pow2_at_least(uint64_t x)
 {
@@ -151,13 +175,17 @@ __host__ __device__ inline uint32_t child_fanout(uint64_t n, uint32_t thresh, ui
 }
 
 // Kernel launchers.
-hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks,
-                        uint64_t* d_sample, uint64_t* d_minmax, uint32_t* d_lcnt, uint64_t* d_lmin,
+// Train njobs models: gather each job's sample, sort it (runs of
+// kSampleBlock in LDS, then merge passes between d_sample and d_tmp), find
+// each leaf's most repeated value and fit.  d_best / d_first: per-leaf tables
+// that start and end at zero.
+hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t max_sample,
+                        uint64_t* d_sample, uint64_t* d_tmp, uint64_t* d_best, uint64_t* d_first,
                         double* d_models, hipStream_t st);
 hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, hipStream_t st);
 hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
-                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint32_t max_fanout,
-                       uint32_t max_leaves, uint32_t flags, hipStream_t st);
+                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint16_t* d_ids,
+                       uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, hipStream_t st);
 hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, hipStream_t st);
 size_t scan_tmp_entries(uint64_t n);
 // Classify every bucket of the round's tasks; the last workgroup to finish
@@ -173,10 +201,11 @@ hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t*
 // to host_ctl.
 hipError_t launch_layout(Task* d_next, ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* d_ctl,
                          RoundCtl* host_ctl, hipStream_t st);
+// d_ids: the bucket of every key of the round, written by the histogram
+// (indexed by the task's cnt_base + position in the task).
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
-                          const double* d_models, const uint64_t* d_pos, const uint8_t* d_skip,
-                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout,
-                          uint32_t max_leaves, uint32_t flags, hipStream_t st);
+                          const uint16_t* d_ids, const uint64_t* d_pos, const uint8_t* d_skip,
+                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, hipStream_t st);
 hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, hipStream_t st);
 hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, hipStream_t st);
 hipError_t launch_touchup(GroupLists groups, const uint32_t* ngroups, const Fill* d_fills, uint32_t nfill,

@@ -82,7 +82,7 @@ __device__ __forceinline__ void wave_count(uint32_t* h, uint32_t b, bool valid)
 template <uint32_t DT, bool MSD>
 __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, const uint64_t* src, uint32_t cnt,
                                           uint32_t* h, unsigned long long* mn, unsigned long long* mx,
-                                          uint32_t flags)
+                                          uint16_t* ids, uint32_t flags)
 {
     constexpr uint32_t STEP = kHistThreads * kHistUnroll;
     const double scale = T.scale;
@@ -115,6 +115,7 @@ __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, const 
                                    : model_bucket<DT>(M, raw[u], scale, offset, fanout, flags);
             wave_count(h, b, valid);
             if (valid) {
+                ids[i] = (uint16_t)b;
                 // Only a new extreme needs an atomic: min only falls and max
                 // only rises, so a stale read can cause an extra atomic but
                 // never a missed one.
@@ -130,7 +131,7 @@ __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, const 
 
 __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32_t ntasks, uint64_t chunk,
                                                        const double* models, uint32_t* cnt, uint64_t* bstat,
-                                                       uint32_t flags)
+                                                       uint16_t* ids, uint32_t flags)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_task;
@@ -157,12 +158,13 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32
     const uint64_t lo = (uint64_t)lc * chunk;
     const uint32_t n = (uint32_t)(min(T.n, lo + chunk) - lo);
     const uint64_t* src = (T.src ? T.scratch : T.keys) + T.start + lo;
+    uint16_t* cid = ids + T.cnt_base + lo;
     if (T.dtype == kF64) {
-        if (msd) hist_body<kF64, true>(T, M, src, n, h, mn, mx, flags);
-        else hist_body<kF64, false>(T, M, src, n, h, mn, mx, flags);
+        if (msd) hist_body<kF64, true>(T, M, src, n, h, mn, mx, cid, flags);
+        else hist_body<kF64, false>(T, M, src, n, h, mn, mx, cid, flags);
     } else {
-        if (msd) hist_body<kU64, true>(T, M, src, n, h, mn, mx, flags);
-        else hist_body<kU64, false>(T, M, src, n, h, mn, mx, flags);
+        if (msd) hist_body<kU64, true>(T, M, src, n, h, mn, mx, cid, flags);
+        else hist_body<kU64, false>(T, M, src, n, h, mn, mx, cid, flags);
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
@@ -175,11 +177,12 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32
 }
 
 hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
-                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint32_t max_fanout,
-                       uint32_t max_leaves, uint32_t flags, hipStream_t st)
+                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint16_t* d_ids,
+                       uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, hipStream_t st)
 {
     size_t smem = (((size_t)max_fanout * 20 + 15) & ~(size_t)15) + model_lds_bytes(max_leaves);
-    k_hist<<<total_chunks, kHistThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_cnt, d_bstat, flags);
+    k_hist<<<total_chunks, kHistThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_cnt, d_bstat, d_ids,
+                                                     flags);
     return hipGetLastError();
 }
 
@@ -206,7 +209,7 @@ constexpr uint32_t kLayoutQ = 9;
 __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& lp, RoundCtl* ctl,
                               RoundCtl* host_ctl)
 {
-    __shared__ unsigned long long s_keys;
+    __shared__ unsigned long long s_keys, s_maxm;
     __shared__ uint32_t s_maxf, s_maxl, s_maxlev;
     __shared__ uint64_t wsum[kLayoutQ][16];
     __shared__ uint64_t carry[kLayoutQ];
@@ -214,6 +217,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
     const uint32_t nt = ctl->ntasks;
     if (threadIdx.x == 0) {
         s_keys = 0;
+        s_maxm = 0;
         s_maxf = 2;
         s_maxl = 1;
         s_maxlev = 0;
@@ -259,6 +263,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
                 m = lp.cap > floor_m ? lp.cap : floor_m;
             L = (uint32_t)(m < lp.leaves ? m : lp.leaves);
             my_maxl = max(my_maxl, L);
+            atomicMax(&s_maxm, (unsigned long long)m);
         }
         const uint64_t nch = valid ? (T.n + chunk - 1) / chunk : 0;
         uint64_t q[kLayoutQ] = {nch,
@@ -269,7 +274,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
                                 m,
                                 L,
                                 local ? model_doubles(L) : 0u,
-                                local ? (m + 2047) / 2048 : 0u};
+                                local ? (m + kSampleBlock - 1) / kSampleBlock : 0u};
         uint64_t x[kLayoutQ];
 #pragma unroll
         for (uint32_t j = 0; j < kLayoutQ; ++j) {
@@ -319,7 +324,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
                 J.leaves = L;
                 J.dtype = T.dtype;
                 J.block0 = (uint32_t)off[8];
-                J.nblocks = (uint32_t)((m + 2047) / 2048);
+                J.nblocks = (uint32_t)((m + kSampleBlock - 1) / kSampleBlock);
                 jobs[off[4]] = J;
             }
             tasks[i] = T;
@@ -342,6 +347,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
         ctl->max_fanout = s_maxf;
         ctl->max_leaves = s_maxl;
         ctl->max_level = s_maxlev;
+        ctl->max_sample = s_maxm;
         __threadfence();
         *host_ctl = *ctl;      // publish to the host without a copy
         __threadfence_system();
@@ -361,7 +367,7 @@ hipError_t launch_layout(Task* d_next, ModelJob* d_jobs, const LayoutParams& lp,
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_classify(const Task* tasks, const uint64_t* pos, const uint64_t* bstat,
+__global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint64_t* pos, const uint64_t* bstat,
                                                   uint32_t thresh, uint32_t param_fanout, Task* next,
                                                   GroupLists groups, Fill* fills, uint8_t* skip,
                                                   uint32_t* task_flags, RoundCtl* ctl, ModelJob* jobs,
@@ -572,7 +578,9 @@ hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t*
                            ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* host_ctl, hipStream_t st)
 {
     size_t smem = (size_t)(max_fanout + 1) * 8 + (size_t)max_fanout * (4 + 4 + 4 + 4 + 4 + 4 + 1) + 64;
-    k_classify<<<ntasks, 256, smem, st>>>(d_tasks, d_pos, d_bstat, thresh, param_fanout, d_next, groups,
+    // a round with a few wide tasks (level 0) gets wide workgroups
+    const uint32_t threads = (ntasks <= 64 && max_fanout >= 1024) ? 1024u : 256u;
+    k_classify<<<ntasks, threads, smem, st>>>(d_tasks, d_pos, d_bstat, thresh, param_fanout, d_next, groups,
                                           d_fills, d_skip, d_task_flags, d_ctl, d_jobs, lp, host_ctl);
     return hipGetLastError();
 }
@@ -582,11 +590,13 @@ hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t*
 constexpr uint32_t kScatterThreads = 1024;
 
 // Scatter: stage one tile in LDS ordered by bucket, then write each bucket's
-// run at its cursor so consecutive lanes write consecutive addresses.  The
-// next tile's keys are loaded while the current one is ranked and written.
-template <uint32_t KPT, uint32_t DT, bool MSD>
-__device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, const uint64_t* src, uint64_t* dst,
-                                             uint32_t n, unsigned char* smem, uint32_t* wsum, uint32_t flags)
+// run at its cursor so consecutive lanes write consecutive addresses.  Bucket
+// ids come from the histogram pass (one u16 per key), so no model is
+// evaluated here.  The next tile's keys and ids are loaded while the current
+// one is ranked and written.
+template <uint32_t KPT>
+__device__ __forceinline__ void scatter_body(const Task& T, const uint64_t* src, const uint16_t* ids, uint64_t* dst,
+                                             uint32_t n, unsigned char* smem, uint32_t* wsum)
 {
     constexpr uint32_t TILE = KPT * kScatterThreads;
     const uint32_t f = T.fanout;
@@ -595,27 +605,30 @@ __device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, con
     uint32_t* tcnt = reinterpret_cast<uint32_t*>(cur + f);
     uint32_t* tstart = tcnt + f;
     uint16_t* sb = reinterpret_cast<uint16_t*>(tstart + f);
-    const double scale = T.scale;
-    const int32_t offset = (int32_t)T.offset;
-    const uint32_t shift = T.shift;
     uint64_t nxt[KPT];
+    uint16_t nid[KPT];
 #pragma unroll
     for (uint32_t u = 0; u < KPT; ++u) {
         const uint32_t i = u * kScatterThreads + threadIdx.x;
         nxt[u] = i < n ? src[i] : 0;
+        nid[u] = i < n ? ids[i] : 0;
     }
     for (uint32_t base = 0; base < n; base += TILE) {
         uint64_t raw[KPT];
         uint32_t bk[KPT];
         uint32_t rk[KPT];
+        uint16_t id[KPT];
 #pragma unroll
-        for (uint32_t u = 0; u < KPT; ++u)
+        for (uint32_t u = 0; u < KPT; ++u) {
             raw[u] = nxt[u];
+            id[u] = nid[u];
+        }
         if (base + TILE < n) {
 #pragma unroll
             for (uint32_t u = 0; u < KPT; ++u) {
                 const uint32_t i = base + TILE + u * kScatterThreads + threadIdx.x;
                 nxt[u] = i < n ? src[i] : 0;
+                nid[u] = i < n ? ids[i] : 0;
             }
         }
 #pragma unroll
@@ -624,8 +637,7 @@ __device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, con
             bk[u] = ~0u;
             rk[u] = 0;
             if (i < n) {
-                const uint32_t b = MSD ? msd_bucket<DT>(raw[u], shift, f)
-                                       : model_bucket<DT>(M, raw[u], scale, offset, f, flags);
+                const uint32_t b = id[u];
                 if (!(cur[b] & kSkipBit)) {
                     bk[u] = b;
                     rk[u] = atomicAdd(&tcnt[b], 1u);
@@ -661,12 +673,11 @@ __device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, con
 
 template <uint32_t KPT>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, uint32_t ntasks, uint64_t chunk,
-                                                             const double* models, const uint64_t* pos,
-                                                             const uint8_t* skip, const uint32_t* task_flags,
-                                                             uint32_t flags)
+                                                             const uint16_t* ids, const uint64_t* pos,
+                                                             const uint8_t* skip, const uint32_t* task_flags)
 {
-    constexpr uint32_t TILE = KPT * kScatterThreads;
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr uint32_t TILE = KPT * kScatterThreads;
     __shared__ uint32_t s_task;
     __shared__ uint32_t wsum[kScatterThreads / 64 + 1];
     if (threadIdx.x == 0)
@@ -679,49 +690,37 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, 
     const uint32_t f = T.fanout;
     uint64_t* cur = reinterpret_cast<uint64_t*>(smem) + TILE;
     uint32_t* tcnt = reinterpret_cast<uint32_t*>(cur + f);
-    void* mlds = smem + (((size_t)TILE * 10 + (size_t)f * 16 + 15) & ~(size_t)15);
     const uint32_t lc = blockIdx.x - T.chunk0;
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
         const uint64_t c = pos[T.cnt_off + (uint64_t)b * T.nchunks + lc] - T.cnt_base;
         cur[b] = skip[(uint64_t)T.bucket_off + b] ? (c | kSkipBit) : c;
         tcnt[b] = 0;
     }
-    SModel M{};
-    const bool msd = T.kind == kMsd;
-    if (!msd)
-        load_model(M, models, T.model, T.leaves, mlds);
     __syncthreads();
     const uint64_t lo = (uint64_t)lc * chunk;
     const uint32_t n = (uint32_t)(min(T.n, lo + chunk) - lo);
     const uint64_t* src = (T.src ? T.scratch : T.keys) + T.start + lo;
     uint64_t* dst = (T.src ? T.keys : T.scratch) + T.start;
-    if (T.dtype == kF64) {
-        if (msd) scatter_body<KPT, kF64, true>(T, M, src, dst, n, smem, wsum, flags);
-        else scatter_body<KPT, kF64, false>(T, M, src, dst, n, smem, wsum, flags);
-    } else {
-        if (msd) scatter_body<KPT, kU64, true>(T, M, src, dst, n, smem, wsum, flags);
-        else scatter_body<KPT, kU64, false>(T, M, src, dst, n, smem, wsum, flags);
-    }
+    scatter_body<KPT>(T, src, ids + T.cnt_base + lo, dst, n, smem, wsum);
 }
 
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
-                          const double* d_models, const uint64_t* d_pos, const uint8_t* d_skip,
-                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, uint32_t max_leaves,
-                          uint32_t flags, hipStream_t st)
+                          const uint16_t* d_ids, const uint64_t* d_pos, const uint8_t* d_skip,
+                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, hipStream_t st)
 {
-    size_t smem = (((size_t)tile * 10 + (size_t)max_fanout * 16 + 15) & ~(size_t)15) + model_lds_bytes(max_leaves);
+    const size_t smem = scatter_lds_bytes(tile, max_fanout);
     switch (tile) {
     case 1024:
-        k_scatter<1><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,
-                                                                  d_task_flags, flags);
+        k_scatter<1><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
+                                                                  d_task_flags);
         break;
     case 2048:
-        k_scatter<2><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,
-                                                                  d_task_flags, flags);
+        k_scatter<2><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
+                                                                  d_task_flags);
         break;
     case 4096:
-        k_scatter<4><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,
-                                                                  d_task_flags, flags);
+        k_scatter<4><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
+                                                                  d_task_flags);
         break;
     default:
         return hipErrorInvalidValue;

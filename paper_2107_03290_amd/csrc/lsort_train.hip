@@ -1,43 +1,114 @@
-// Model training: sample, per-leaf statistics, spline fit (Sec. 6.1).
+// Model training on the device (Sec. 6.1: two layers, 1% sample; the
+// procedure itself is reading R14 of the model):
+//   k_train_sample     gather each job's sample as order-preserving words
+//   k_train_sort_runs  sort runs of kSampleBlock words in LDS
+//   k_train_merge      merge passes: every word moves to its rank in the
+//                      merged pair of runs (its index plus its count in the
+//                      other run), so a pass is one gather-free scatter
+//   k_train_modes      per leaf: its most repeated value (longest run of equal
+//                      values, the smallest on ties) and its first sample
+//   k_train_fit        knots (the most repeated value of a leaf when it holds
+//                      2+ copies and 1/L of the sample, else the leaf's
+//                      smallest value), mid-ranks, segments; tables to zero
 #include "lsort_device.h"
 
 #pragma clang fp contract(off)
 
 namespace lsort {
 
-// ----------------------------------------------------------- model training --
+constexpr uint64_t kOrdNegInf = 0x000fffffffffffffull;   // order word of -inf
+constexpr uint64_t kOrdPosInf = 0xfff0000000000000ull;   // order word of +inf
 
-constexpr uint32_t kSampleBlock = 2048;   // samples per training block
-
+// Job of training block blk (jobs sorted by block0).
 __device__ __forceinline__ uint32_t find_job(const ModelJob* jobs, uint32_t njobs, uint32_t blk)
 {
     uint32_t lo = 0, hi = njobs;
     while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
+        const uint32_t mid = (lo + hi) >> 1;
         if (jobs[mid].block0 <= blk) lo = mid; else hi = mid;
     }
     return lo;
 }
 
-// Training tables use 0 as their neutral value and the fit kernel returns
-// them to 0 after use, so no initialisation pass is needed: per job
-// minmax = {~min, max} of the finite sample words, per leaf lcnt = count and
-// lmin = ~(smallest word).
+// Job owning sample word g (jobs sorted by sample_off).
+__device__ __forceinline__ uint32_t find_job_of(const ModelJob* jobs, uint32_t njobs, uint64_t g)
+{
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (jobs[mid].sample_off <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
-// Gather the sample (order-preserving words) and reduce its finite range.
-__global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint32_t njobs,
-                                                      uint64_t* sample, uint64_t* minmax)
+// Finite part [lo, hi) of a sorted sample S[0..m): non-finite words sit at
+// both ends (negative ones up to -inf's word, positive ones from +inf's).
+__device__ inline void finite_range(const uint64_t* S, uint64_t m, uint32_t dt, uint64_t& lo, uint64_t& hi)
+{
+    if (dt != kF64) {
+        lo = 0;
+        hi = m;
+        return;
+    }
+    uint64_t a = 0, b = m;
+    while (a < b) {
+        const uint64_t mid = (a + b) >> 1;
+        if (S[mid] <= kOrdNegInf) a = mid + 1; else b = mid;
+    }
+    lo = a;
+    b = m;
+    while (a < b) {
+        const uint64_t mid = (a + b) >> 1;
+        if (S[mid] < kOrdPosInf) a = mid + 1; else b = mid;
+    }
+    hi = a;
+}
+
+// First index in [a, b) whose value exceeds x (values non-decreasing).
+__device__ inline uint64_t value_upper(const uint64_t* S, uint64_t a, uint64_t b, double x, uint32_t dt)
+{
+    while (a < b) {
+        const uint64_t mid = (a + b) >> 1;
+        if (ord_value(S[mid], dt) > x) b = mid; else a = mid + 1;
+    }
+    return a;
+}
+
+struct Root {
+    double xmin, xmax, r0, rs;
+};
+
+__device__ inline Root root_of(const uint64_t* S, uint64_t lo, uint64_t hi, uint32_t dt, uint32_t L)
+{
+    Root R;
+    R.xmin = ord_value(S[lo], dt);
+    R.xmax = ord_value(S[hi - 1], dt);
+    R.r0 = root_coord(R.xmin);
+    const double r1 = root_coord(R.xmax);
+    R.rs = r1 > R.r0 ? (double)L / (r1 - R.r0) : 0.0;
+    return R;
+}
+
+__device__ __forceinline__ uint32_t root_leaf(double x, const Root& R, uint32_t L)
+{
+    const double t = (root_coord(x) - R.r0) * R.rs;
+    if (!(t >= 1.0))
+        return 0;
+    if (t >= (double)(L - 1u))
+        return L - 1u;
+    return (uint32_t)t;
+}
+
+// Gather the sample (order-preserving words), 16 independent loads per lane.
+__global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint32_t njobs, uint64_t* sample)
 {
     __shared__ uint32_t s_job;
-    __shared__ uint64_t s_lo[4], s_hi[4];
     if (threadIdx.x == 0)
         s_job = find_job(jobs, njobs, blockIdx.x);
     __syncthreads();
-    const uint32_t j = s_job;
-    const ModelJob J = jobs[j];
+    const ModelJob J = jobs[s_job];
     const uint64_t t0 = (uint64_t)(blockIdx.x - J.block0) * kSampleBlock;
-    uint64_t lo = ~0ull, hi = 0;
-    constexpr uint32_t U = kSampleBlock / 256;    // independent gathers in flight per lane
+    constexpr uint32_t U = kSampleBlock / 256;
     uint64_t raw[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
@@ -47,193 +118,281 @@ __global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
         const uint64_t t = t0 + u * 256 + threadIdx.x;
-        if (t < J.m) {
-            const uint64_t o = to_ord(raw[u], J.dtype);
-            sample[J.sample_off + t] = o;
-            if (!nonfinite(raw[u], J.dtype)) {
-                lo = o < lo ? o : lo;
-                hi = o > hi ? o : hi;
-            }
-        }
-    }
-    for (uint32_t d = 32; d > 0; d >>= 1) {
-        uint64_t a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
-        lo = a < lo ? a : lo;
-        hi = b > hi ? b : hi;
-    }
-    if ((threadIdx.x & 63u) == 0) {
-        s_lo[threadIdx.x >> 6] = lo;
-        s_hi[threadIdx.x >> 6] = hi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (uint32_t w = 1; w < blockDim.x / 64; ++w) {
-            lo = s_lo[w] < lo ? s_lo[w] : lo;
-            hi = s_hi[w] > hi ? s_hi[w] : hi;
-        }
-        if (lo != ~0ull) {
-            atomicMax((unsigned long long*)&minmax[2 * j], (unsigned long long)~lo);
-            atomicMax((unsigned long long*)&minmax[2 * j + 1], (unsigned long long)hi);
-        }
+        if (t < J.m)
+            sample[J.sample_off + t] = to_ord(raw[u], J.dtype);
     }
 }
 
-__device__ __forceinline__ void root_params(const uint64_t* minmax, uint32_t j, uint32_t dt, uint32_t L,
-                                            double& xmin, double& xmax, double& rs, bool& any)
+// Sort the block's run of up to kSampleBlock sample words in LDS.
+__global__ __launch_bounds__(256) void k_train_sort_runs(const ModelJob* jobs, uint32_t njobs, uint64_t* sample)
 {
-    uint64_t lo = ~minmax[2 * j], hi = minmax[2 * j + 1];
-    any = lo != ~0ull;
-    xmin = any ? ord_value(lo, dt) : 0.0;
-    xmax = any ? ord_value(hi, dt) : 0.0;
-    rs = (xmax > xmin) ? (double)L / (xmax - xmin) : 0.0;
-}
-
-__device__ __forceinline__ uint32_t root_leaf(double x, double xmin, double rs, uint32_t L)
-{
-    double t = (x - xmin) * rs;
-    if (!(t >= 1.0))
-        return 0;
-    if (t >= (double)(L - 1u))
-        return L - 1u;
-    return (uint32_t)t;
-}
-
-// Per-leaf sample counts and minima, aggregated in LDS first.
-__global__ __launch_bounds__(256) void k_train_leaves(const ModelJob* jobs, uint32_t njobs,
-                                                      const uint64_t* sample, const uint64_t* minmax,
-                                                      uint32_t* lcnt, uint64_t* lmin)
-{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t* s = reinterpret_cast<uint64_t*>(smem);
     __shared__ uint32_t s_job;
-    __shared__ uint32_t c[kMaxLeaves];
-    __shared__ unsigned long long mn[kMaxLeaves];
     if (threadIdx.x == 0)
         s_job = find_job(jobs, njobs, blockIdx.x);
     __syncthreads();
-    const uint32_t j = s_job;
-    const ModelJob J = jobs[j];
-    const uint32_t L = J.leaves;
-    for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
-        c[k] = 0;
-        mn[k] = ~0ull;
-    }
-    double xmin, xmax, rs;
-    bool any;
-    root_params(minmax, j, J.dtype, L, xmin, xmax, rs, any);
-    __syncthreads();
+    const ModelJob J = jobs[s_job];
     const uint64_t t0 = (uint64_t)(blockIdx.x - J.block0) * kSampleBlock;
-    for (uint32_t i = threadIdx.x; i < kSampleBlock; i += blockDim.x) {
-        uint64_t t = t0 + i;
-        if (t >= J.m)
-            break;
-        uint64_t o = sample[J.sample_off + t];
-        uint64_t raw = from_ord(o, J.dtype);
-        if (nonfinite(raw, J.dtype))
-            continue;
-        uint32_t k = root_leaf(key_value(raw, J.dtype), xmin, rs, L);
-        atomicAdd(&c[k], 1u);
-        atomicMin(&mn[k], (unsigned long long)o);
+    if (t0 >= J.m)
+        return;
+    const uint32_t n = (uint32_t)min((uint64_t)kSampleBlock, J.m - t0);
+    uint32_t logN = 4;
+    while ((1u << logN) < n)
+        ++logN;
+    uint64_t* run = sample + J.sample_off + t0;
+    for (uint32_t i = threadIdx.x; i < (1u << logN); i += 256)
+        s[base_pad(i)] = i < n ? run[i] : ~0ull;
+    __syncthreads();
+    lds_bitonic<256>(s, logN);
+    for (uint32_t i = threadIdx.x; i < n; i += 256)
+        run[i] = s[base_pad(i)];
+}
+
+// One merge pass: runs of w words (sorted) become runs of 2w.  A word of the
+// left run lands after the right run's smaller words, a word of the right run
+// after the left run's words not above it, so equal words keep their order.
+__global__ __launch_bounds__(256) void k_train_merge(const ModelJob* jobs, uint32_t njobs, const uint64_t* src,
+                                                     uint64_t* dst, uint64_t w, uint64_t total)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= total)
+        return;
+    const ModelJob J = jobs[find_job_of(jobs, njobs, g)];
+    const uint64_t t = g - J.sample_off;
+    if (t >= J.m)
+        return;
+    const uint64_t* S = src + J.sample_off;
+    const uint64_t p0 = t / (2 * w) * (2 * w);
+    const uint64_t a1 = min(p0 + w, J.m), b1 = min(p0 + 2 * w, J.m);
+    const uint64_t x = S[t];
+    uint64_t pos;
+    if (t < a1) {
+        uint64_t lo = a1, hi = b1;                 // right-run words below x
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (S[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        pos = t + (lo - a1);
+    } else {
+        uint64_t lo = p0, hi = a1;                 // left-run words not above x
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (S[mid] <= x) lo = mid + 1; else hi = mid;
+        }
+        pos = (t - a1) + lo;
+    }
+    dst[J.sample_off + pos] = x;
+}
+
+// Per leaf: longest run of equal values as (length << 32 | ~start) and the
+// complemented first sample index, reduced in LDS before the global atomics.
+__global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint32_t njobs, const uint64_t* sorted,
+                                                     uint64_t* best, uint64_t* firstc)
+{
+    __shared__ uint32_t s_job;
+    __shared__ unsigned long long s_best[kMaxLeaves], s_first[kMaxLeaves];
+    __shared__ uint64_t s_lo, s_hi;
+    if (threadIdx.x == 0) {
+        s_job = find_job(jobs, njobs, blockIdx.x);
+        const ModelJob J0 = jobs[s_job];
+        uint64_t lo, hi;
+        finite_range(sorted + J0.sample_off, J0.m, J0.dtype, lo, hi);
+        s_lo = lo;
+        s_hi = hi;
     }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
-        if (c[k]) {
-            atomicAdd(&lcnt[J.leaf_off + k], c[k]);
-            atomicMax((unsigned long long*)&lmin[J.leaf_off + k], ~mn[k]);
+    const ModelJob J = jobs[s_job];
+    const uint32_t L = J.leaves;
+    const uint64_t lo = s_lo, hi = s_hi;
+    const uint64_t t0 = (uint64_t)(blockIdx.x - J.block0) * kSampleBlock;
+    const uint64_t a = max(t0, lo), b = min(t0 + kSampleBlock, hi);
+    if (a >= b)
+        return;                                        // the whole block leaves together
+    for (uint32_t k = threadIdx.x; k < L; k += 256) {
+        s_best[k] = 0;
+        s_first[k] = 0;
+    }
+    const uint64_t* S = sorted + J.sample_off;
+    const Root R = root_of(S, lo, hi, J.dtype, L);
+    __syncthreads();
+    // each lane walks 16 consecutive words; a run's length is counted in
+    // place and only a run reaching past the lane's range is searched for
+    constexpr uint32_t kPer = kSampleBlock / 256;
+    const uint64_t r0 = a + (uint64_t)threadIdx.x * kPer;
+    const uint64_t r1 = min(r0 + kPer, b);
+    for (uint64_t t = r0; t < r1;) {
+        const double x = ord_value(S[t], J.dtype);
+        uint64_t e = t + 1;
+        while (e < r1 && ord_value(S[e], J.dtype) == x)
+            ++e;
+        const bool start = t == lo || ord_value(S[t - 1], J.dtype) != x;
+        if (start) {
+            if (e == r1)
+                e = value_upper(S, r1, hi, x, J.dtype);
+            const uint32_t k = root_leaf(x, R, L);
+            const uint64_t rel = t - lo;
+            atomicMax(&s_best[k], (unsigned long long)(((e - t) << 32) | (0xffffffffull - rel)));
+            atomicMax(&s_first[k], (unsigned long long)~rel);
+        }
+        t = e > r1 ? r1 : e;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < L; k += 256) {
+        if (s_best[k]) {
+            atomicMax((unsigned long long*)&best[J.leaf_off + k], s_best[k]);
+            atomicMax((unsigned long long*)&firstc[J.leaf_off + k], s_first[k]);
         }
     }
 }
 
-// Fit: knots at leaf minima with exact eCDF values, segments to the next knot.
-// Prefix counts, previous and next non-empty leaf come from block scans.
-__global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, uint64_t* minmax, uint32_t* lcnt,
-                                                   uint64_t* lmin, double* models)
+// Knots and segments of one job's model (one block per job).
+__global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const uint64_t* sorted, uint64_t* best,
+                                                   uint64_t* firstc, double* models)
 {
-    __shared__ uint64_t below[kMaxLeaves];
     __shared__ int32_t prv[kMaxLeaves];
     __shared__ int32_t nxt[kMaxLeaves];      // reversed index
-    __shared__ uint64_t ws64[5];
-    __shared__ int32_t ws32[5];
-    const uint32_t j = blockIdx.x;
-    const ModelJob J = jobs[j];
+    __shared__ uint32_t kB[kMaxLeaves], kd[kMaxLeaves];   // knot: sample values below it, its copies
+    __shared__ int32_t ws32[17];
+    __shared__ uint64_t s_lo, s_hi, s_run0;
+    const ModelJob J = jobs[blockIdx.x];
     const uint32_t L = J.leaves;
-    const uint32_t* cnt = lcnt + J.leaf_off;
+    const uint64_t* S = sorted + J.sample_off;
+    if (threadIdx.x == 0) {
+        uint64_t lo, hi;
+        finite_range(S, J.m, J.dtype, lo, hi);
+        s_lo = lo;
+        s_hi = hi;
+        s_run0 = hi > lo ? value_upper(S, lo + 1, hi, ord_value(S[lo], J.dtype), J.dtype) - lo : 0;
+    }
+    const uint64_t* bt = best + J.leaf_off;
     for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
-        const uint32_t c = cnt[k];
-        below[k] = c;
-        prv[k] = c ? (int32_t)k : -1;
-        nxt[L - 1 - k] = c ? (int32_t)k : 0x7fffffff;
+        const bool ne = bt[k] != 0;
+        prv[k] = ne ? (int32_t)k : -1;
+        nxt[L - 1 - k] = ne ? (int32_t)k : 0x7fffffff;
     }
     __syncthreads();
-    const uint64_t mfin = block_scan_op<uint64_t>(below, L, 0ull, AddU64(), ws64);
     block_scan_op<int32_t>(prv, L, -1, MaxI32(), ws32);
-    block_scan_op<int32_t>(nxt, L, 0x7fffffff, MinI32(), ws32);
-    double xmin, xmax, rs;
-    bool any;
-    root_params(minmax, j, J.dtype, L, xmin, xmax, rs, any);
+    const int32_t first_leaf = block_scan_op<int32_t>(nxt, L, 0x7fffffff, MinI32(), ws32);
+    const uint64_t lo = s_lo, hi = s_hi;
+    const uint64_t mfin = hi - lo;
     double* g = models + J.model_off;
-    double* seg = g + 4;                                   // per leaf {X, y, s, yhi}
-    uint32_t* prev = reinterpret_cast<uint32_t*>(g + 4 + 4 * (size_t)L);
-    if (threadIdx.x == 0) {
-        g[0] = mfin ? xmin : 0.0;
-        g[1] = mfin ? xmax : 0.0;
-        g[2] = mfin ? rs : 0.0;
-        g[3] = (double)mfin;
-    }
+    double2* seg = reinterpret_cast<double2*>(g + kModelSeg);     // {X, ylo}, {s, yhi}
+    double* gym = g + model_ym_off(L);
+    double* gy = g + model_y_off(L);
+    double* gy1 = g + model_y1_off(L);
+    uint32_t* prev = reinterpret_cast<uint32_t*>(g + model_prev_off(L));
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
-        double* o = seg + 4 * (size_t)k;
-        if (!mfin) {
-            o[0] = inf;
-            o[1] = 0.0;
-            o[2] = 0.0;
-            o[3] = 0.0;
-            prev[k] = kNoPrev;
-            continue;
+    if (mfin == 0) {
+        for (uint32_t k = threadIdx.x; k <= L; k += blockDim.x) {
+            seg[2 * k] = make_double2(inf, 0.0);
+            seg[2 * k + 1] = make_double2(0.0, 0.0);
+            gym[k] = 0.0;
+            gy[k] = 0.0;
+            gy1[k] = 0.0;
+            if (k < L)
+                prev[k] = kNoPrev;
         }
-        const double yk = (double)below[k] / (double)mfin;
-        prev[k] = prv[k] < 0 ? kNoPrev : (uint32_t)prv[k];
-        if (!cnt[k]) {
-            o[0] = inf;
-            o[1] = yk;
-            o[2] = 0.0;
-            o[3] = yk;
-            continue;
+        if (threadIdx.x == 0)
+            g[0] = g[1] = g[2] = g[3] = 0.0;
+    } else {
+        const Root R = root_of(S, lo, hi, J.dtype, L);
+        const double mf = (double)mfin, m2 = (double)(2 * mfin);
+        for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
+            const uint64_t key = bt[k];
+            if (!key)
+                continue;
+            const uint64_t len = key >> 32;
+            if (len >= 2 && len * L >= mfin) {
+                kB[k] = (uint32_t)(0xffffffffull - (key & 0xffffffffull));
+                kd[k] = (uint32_t)len;
+            } else {
+                const uint64_t f0 = ~firstc[J.leaf_off + k];
+                kB[k] = (uint32_t)f0;
+                kd[k] = (uint32_t)(value_upper(S, lo + f0 + 1, hi, ord_value(S[lo + f0], J.dtype), J.dtype) -
+                                   (lo + f0));
+            }
         }
-        const double Xk = ord_value(~lmin[J.leaf_off + k], J.dtype);
-        double Xh = xmax, yh = 1.0;
-        const int32_t q = nxt[L - 1 - k];          // first non-empty leaf after k
-        if (q != 0x7fffffff) {
-            Xh = ord_value(~lmin[J.leaf_off + q], J.dtype);
-            yh = (double)below[q] / (double)mfin;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            g[0] = R.xmin;
+            g[1] = R.xmax;
+            g[2] = R.rs;
+            g[3] = mf;
         }
-        double sl = (yh - yk) / (Xh - Xk);
-        if (!(sl > 0.0) || __builtin_isinf(sl))
-            sl = 0.0;
-        o[0] = Xk;
-        o[1] = yk;
-        o[2] = sl;
-        o[3] = yh;
+        // knot k (k == L: the start knot at the sample minimum) and the
+        // segment above it
+        for (uint32_t k = threadIdx.x; k <= L; k += blockDim.x) {
+            uint64_t B = 0, d = 0;
+            bool knot = true;
+            int32_t q;                                // next non-empty leaf
+            if (k < L) {
+                knot = bt[k] != 0;
+                B = knot ? kB[k] : 0;
+                d = knot ? kd[k] : 0;
+                q = nxt[L - 1 - k];
+                prev[k] = prv[k] < 0 ? kNoPrev : (uint32_t)prv[k];
+            } else {
+                d = s_run0;
+                q = first_leaf;
+            }
+            if (!knot) {
+                // empty leaf: constant at the sample count below it
+                const uint64_t nb = q != 0x7fffffff ? ~firstc[J.leaf_off + q] : mfin;
+                const double v = (double)nb / mf;
+                seg[2 * k] = make_double2(inf, v);
+                seg[2 * k + 1] = make_double2(0.0, v);
+                gym[k] = v;
+                gy[k] = v;
+                gy1[k] = v;
+                continue;
+            }
+            const double X = k < L ? ord_value(S[lo + B], J.dtype) : R.xmin;
+            const double ylo = (double)(2 * (B + d) - 1) / m2;
+            double Xh = R.xmax, yh = 1.0;
+            if (q != 0x7fffffff) {
+                const uint64_t Bq = kB[q];
+                Xh = ord_value(S[lo + Bq], J.dtype);
+                yh = (double)(2 * Bq + 1) / m2;
+            }
+            double sl = (yh - ylo) / (Xh - X);
+            if (!(sl > 0.0) || __builtin_isinf(sl))
+                sl = 0.0;
+            seg[2 * k] = make_double2(X, ylo);
+            seg[2 * k + 1] = make_double2(sl, yh);
+            gym[k] = (double)(2 * B + d) / m2;
+            gy[k] = (double)B / mf;
+            gy1[k] = (double)(B + d) / mf;
+        }
     }
     __syncthreads();
-    // leave the tables neutral for the next training call
+    // leave the tables at zero for the next training call
     for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
-        lcnt[J.leaf_off + k] = 0;
-        lmin[J.leaf_off + k] = 0;
-    }
-    if (threadIdx.x == 0) {
-        minmax[2 * j] = 0;
-        minmax[2 * j + 1] = 0;
+        best[J.leaf_off + k] = 0;
+        firstc[J.leaf_off + k] = 0;
     }
 }
 
-hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t* d_sample,
-                        uint64_t* d_minmax, uint32_t* d_lcnt, uint64_t* d_lmin, double* d_models,
-                        hipStream_t st)
+hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t max_sample,
+                        uint64_t* d_sample, uint64_t* d_tmp, uint64_t* d_best, uint64_t* d_first,
+                        double* d_models, hipStream_t st)
 {
     if (!njobs)
         return hipSuccess;
-    k_train_sample<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, d_sample, d_minmax);
-    k_train_leaves<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, d_sample, d_minmax, d_lcnt, d_lmin);
-    k_train_fit<<<njobs, 256, 0, st>>>(d_jobs, d_minmax, d_lcnt, d_lmin, d_models);
+    // every job's sample lies inside its blocks: sample_off + m <= block0 * kSampleBlock + ...
+    const uint64_t total = (uint64_t)total_blocks * kSampleBlock;
+    k_train_sample<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, d_sample);
+    k_train_sort_runs<<<total_blocks, 256, (size_t)base_pad(kSampleBlock) * 8, st>>>(d_jobs, njobs, d_sample);
+    uint64_t* src = d_sample;
+    uint64_t* dst = d_tmp;
+    for (uint64_t w = kSampleBlock; w < max_sample; w *= 2) {
+        k_train_merge<<<(uint32_t)((total + 255) / 256), 256, 0, st>>>(d_jobs, njobs, src, dst, w, total);
+        uint64_t* t = src;
+        src = dst;
+        dst = t;
+    }
+    k_train_modes<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, src, d_best, d_first);
+    k_train_fit<<<njobs, 256, 0, st>>>(d_jobs, src, d_best, d_first, d_models);
     return hipGetLastError();
 }
 

@@ -15,12 +15,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lsort_oracle.c")
 
 MUTANTS = {
-    "knot_counts_own_leaf": ("M->y[k] = (double)below / (double)mfin;",
-                             "M->y[k] = (double)(below + cnt[k]) / (double)mfin;"),
+    "knot_counts_own_copies": ("M->y[k] = (double)B / (double)M->mfin;",
+                               "M->y[k] = (double)(B + d) / (double)M->mfin;"),
+    "segment_starts_at_mid_rank": ("M->ylo[k] = (double)(2 * (B + d) - 1) / m2;", "M->ylo[k] = M->ym[k];"),
     "segment_upper_clamp_dropped": ("    if (F > M->yhi[j])\n        F = M->yhi[j];\n", ""),
-    "slope_transposed": ("double sl = (yh - M->y[k]) / (Xh - M->X[k]);",
-                         "double sl = (Xh - M->X[k]) / (yh - M->y[k]);"),
-    "root_from_xmax": ("double t = (x - M->xmin) * M->rs;", "double t = (x - M->xmax) * M->rs;"),
+    "slope_transposed": ("double sl = (yh - M->ylo[k]) / (Xh - M->X[k]);",
+                         "double sl = (Xh - M->X[k]) / (yh - M->ylo[k]);"),
+    "root_from_xmax": ("double t = (root_coord(x) - M->r0) * M->rs;",
+                       "double t = (root_coord(x) - root_coord(M->xmax)) * M->rs;"),
+    "knot_is_leaf_minimum": ("if (e - a > best[k]) {", "if (best[k] == 0) {"),
     "no_previous_knot": ("uint32_t j = (x >= M->X[k]) ? k : model_prev(M, k);", "uint32_t j = k;"),
     "level_offset_sign": ("int64_t q = (int64_t)v - B->offset;", "int64_t q = (int64_t)v + B->offset;"),
     "tail_flush_skips_last": ("for (uint32_t i = 0; i < f && rc == ORC_OK; ++i) {\n        uint32_t s = fsz[i];",

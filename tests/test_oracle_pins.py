@@ -64,20 +64,23 @@ def test_model_training_worked_example():
     m = oracle.train_sample(np.array(g["sample"]), g["leaves"])
     e = g["expected"]
     want = [q(e["xmin"]), q(e["xmax"]), q(e["rs"]), q(e["mfin"])]
-    want += [q(v) for v in e["leaf0"]] + [q(v) for v in e["leaf1"]]
+    want += [q(v) for v in e["leaf0"]] + [q(v) for v in e["leaf1"]] + [q(v) for v in e["start"]]
     assert m.tolist() == want
     F = oracle.model_eval(m, g["leaves"], np.array(g["eval_x"]))
     assert F.tolist() == [q(v) for v in g["eval_F"]]
 
 
 def _leaves(model):
-    return model[4::4], model[5::4], model[6::4], model[7::4]
+    """X, y, ym, y1, ylo, yhi, s of the L leaf knots, then the start knot."""
+    return tuple(model[4 + c::7] for c in range(7))
 
 
 @pytest.mark.parametrize("family", ["uniform", "normal", "lognormal", "zipfdup", "u64mixed"])
 def test_model_knots_are_exact_ecdf(family):
     # Sec. 2: the model returns the count of keys less than x, scaled; at a
-    # knot X_k that count over the sample is known exactly.
+    # knot X the sample counts below it and at it are known exactly:
+    # y = #(< X)/m', ym = (#(< X) + #(<= X))/(2m'), y1 = #(<= X)/m', and the
+    # segment above the knot starts from y1.
     r = np.random.default_rng(11)
     if family == "uniform":
         a = r.random(50_000)
@@ -95,18 +98,84 @@ def test_model_knots_are_exact_ecdf(family):
     sv = sample.astype(np.float64)
     m_fin = np.isfinite(sv).sum()
     assert model[3] == m_fin
-    X, y, yhi, s = _leaves(model)
+    X, y, ym, y1, ylo, yhi, s = _leaves(model)
+    assert X.size == L + 1
+    assert X[L] == sv.min()                     # the start knot
     knots = np.flatnonzero(np.isfinite(X))
-    assert knots.size >= 1
-    assert X[knots[0]] == sv.min()
+    assert knots.size >= 2
+    assert np.all(np.diff(X[knots[:-1]]) > 0)   # leaf knots increase
     for k in knots:
         below = int((sv < X[k]).sum())
+        upto = int((sv <= X[k]).sum())
         assert y[k] == below / m_fin
+        assert y1[k] == upto / m_fin
+        assert ym[k] == (below + upto) / (2 * m_fin)
+        assert ylo[k] == (2 * upto - 1) / (2 * m_fin)       # mid-rank of the last copy
         assert X[k] in sv                       # knots are sample values
-    Fk = oracle.model_eval(model, L, np.asarray(X[knots], dtype=np.float64).astype(a.dtype)
-                           if a.dtype == np.float64 else X[knots].astype(np.uint64))
     if a.dtype == np.float64:
-        assert np.array_equal(Fk, y[knots])
+        Fk = oracle.model_eval(model, L, np.asarray(X[knots], dtype=np.float64))
+        assert np.array_equal(Fk, ym[knots])
+        # just above a knot (below the next one) F is at least the mid-rank
+        # of the knot's last copy, just below it at most that of its first
+        order = np.argsort(X[knots])
+        kk = knots[order]
+        lk = X[kk]
+        above = np.nextafter(lk, np.inf)
+        inside = above < np.append(lk[1:], np.inf)
+        Fa = oracle.model_eval(model, L, above[inside])
+        assert np.all(Fa >= ylo[kk][inside])
+        below_k = np.nextafter(lk[1:], -np.inf)
+        ok = below_k > lk[:-1]
+        Fb = oracle.model_eval(model, L, below_k[ok])
+        assert np.all(Fb <= ((2 * (y[kk[1:]] * m_fin) + 1) / (2 * m_fin))[ok])
+
+
+def test_model_knot_is_the_most_repeated_value_nearby():
+    # A leaf's knot is its most repeated sample value when that value holds
+    # at least 1/L of the sample.  A leaf lies between the knots around it,
+    # so no value that heavy sits strictly between two consecutive knots
+    # unless one of them repeats at least as often; the most repeated value
+    # of the whole sample is a knot.
+    r = np.random.default_rng(14)
+    a = W.zipf_dup(r, 60_000, 0.97)
+    L = 48
+    model, idx = oracle.train(a, leaves=L, sample_rate=0.2)
+    sv = a[idx.astype(np.int64)]
+    m = sv.size
+    vals, mult = np.unique(sv, return_counts=True)
+    X = _leaves(model)[0]
+    knots = np.unique(X[np.isfinite(X)])
+    km = {v: c for v, c in zip(vals, mult)}
+    heavy = (mult >= 2) & (mult * L >= m)
+    assert heavy.sum() >= 3
+    for lo, hi in zip(knots[:-1], knots[1:]):
+        inner = (vals > lo) & (vals < hi) & heavy
+        if inner.any():
+            assert mult[inner].max() <= max(km[lo], km[hi])
+    assert vals[np.argmax(mult)] in knots
+    # with no value that heavy every knot is its leaf's smallest value, so
+    # no sample value lies strictly below the lowest leaf knot but above xmin
+    u = np.random.default_rng(15).random(20_000)
+    model, idx = oracle.train(u, leaves=L, sample_rate=0.2)
+    su = u[idx.astype(np.int64)]
+    Xu = _leaves(model)[0][:L]
+    first_knot = Xu[np.isfinite(Xu)].min()
+    assert first_knot == su.min()
+
+
+def test_model_isolates_a_heavy_sample_value():
+    # A value holding at least two buckets' worth of the sample falls strictly
+    # between the keys below and above it: its level-0 bucket holds it alone.
+    r = np.random.default_rng(13)
+    f = 64
+    heavy = 0.37
+    a = np.concatenate([r.random(40_000), np.full(4_000, heavy)])
+    r.shuffle(a)
+    model, _ = oracle.train(a, leaves=32, sample_rate=0.05)
+    b = oracle.bucket(model, 32, a, scale=f, offset=0, fanout=f)
+    hb = b[a == heavy]
+    assert np.all(hb == hb[0])
+    assert not np.any((b == hb[0]) & (a != heavy))
 
 
 @pytest.mark.parametrize("family", ["uniform", "lognormal", "zipfdup", "specials"])
