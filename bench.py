@@ -397,6 +397,7 @@ def main():
     ap.add_argument("--leaves", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--base", type=int, default=0)
+    ap.add_argument("--sample-cap", type=int, default=-1, help="cap on a model's sample (-1: library default)")
     ap.add_argument("--cpu-sample", type=int, default=200_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verify", action="store_true", help="check the sorted output against numpy")
@@ -438,6 +439,8 @@ def main():
                  ("base_threshold", args.base)):
         if v:
             kw[k] = v
+    if args.sample_cap >= 0:
+        kw["sample_cap"] = args.sample_cap
     p = ls.params(flags=ls.FLAG_PROFILE, **kw)
     stream = torch.cuda.current_stream(dev)
 
@@ -486,7 +489,7 @@ def main():
         "dtype": "f64" if keys.dtype == np.float64 else "u64",
         "data": "synthetic (seeded generator; no dataset)",
         "config": {"workload": wname, "n": n, "fanout": p.fanout, "leaves": p.leaves, "tile": p.tile,
-                   "base_threshold": p.base_threshold, "sample_rate": p.sample_rate},
+                   "base_threshold": p.base_threshold, "sample_rate": p.sample_rate, "sample_cap": p.sample_cap},
         "roofline": roofline(prof, wname),
         "kernel_ms_per_step": {k: prof[k][0] / K for k in prof},
         "kernel_GBps": {k: (prof[k][2] / (prof[k][0] / 1e3) / 1e9 if prof[k][0] else 0.0) for k in prof},

@@ -61,7 +61,7 @@ typedef enum { LS_F64 = 1, LS_U64 = 2 } ls_dtype;
  * Zero fields take the library defaults.  None of them changes the result. */
 typedef struct {
     uint32_t struct_size;      /* sizeof(ls_params) */
-    uint32_t fanout;           /* f: buckets per partition, 2..4096 (default 2048) */
+    uint32_t fanout;           /* f: buckets per partition, 2..4096 (default 1024) */
     uint32_t leaves;           /* L: leaf models of the two-layer model, 1..1024 (default 1024) */
     uint32_t tile;             /* keys staged per partition tile in LDS 1024, 2048 or 4096 (default 4096) */
     uint32_t base_threshold;   /* buckets of at most this many keys are sorted in LDS, in groups of < 2x (default 4096, max 4096) */

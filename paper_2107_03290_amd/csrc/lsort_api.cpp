@@ -23,7 +23,7 @@ using namespace lsort;
 
 namespace {
 
-constexpr uint32_t kDefaultFanout = 2048;
+constexpr uint32_t kDefaultFanout = 1024;
 constexpr uint32_t kDefaultLeaves = 1024;
 constexpr uint32_t kDefaultTile = 4096;
 constexpr uint32_t kDefaultBase = 4096;

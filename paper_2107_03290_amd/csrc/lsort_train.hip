@@ -185,13 +185,18 @@ __global__ __launch_bounds__(256) void k_train_merge(const ModelJob* jobs, uint3
     dst[J.sample_off + pos] = x;
 }
 
-// Per leaf: longest run of equal values as (length << 32 | ~start) and the
-// complemented first sample index, reduced in LDS before the global atomics.
+// Per leaf: the longest run of equal values as (length << 32 | ~start) and
+// the first run as (~start << 32 | length), both reduced with atomicMax in
+// LDS before the global atomics.  The block's sorted words are staged in LDS
+// and each lane walks 16 consecutive ones; only a run that reaches past the
+// lane's range is searched for in global memory.
 __global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint32_t njobs, const uint64_t* sorted,
                                                      uint64_t* best, uint64_t* firstc)
 {
+    constexpr uint32_t kPer = kSampleBlock / 256;
     __shared__ uint32_t s_job;
     __shared__ unsigned long long s_best[kMaxLeaves], s_first[kMaxLeaves];
+    __shared__ double s_val[kSampleBlock + 1];
     __shared__ uint64_t s_lo, s_hi;
     if (threadIdx.x == 0) {
         s_job = find_job(jobs, njobs, blockIdx.x);
@@ -209,33 +214,36 @@ __global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint3
     const uint64_t a = max(t0, lo), b = min(t0 + kSampleBlock, hi);
     if (a >= b)
         return;                                        // the whole block leaves together
+    const uint64_t* S = sorted + J.sample_off;
+    // s_val[i] = value of word a - 1 + i (i = 0 is the word before the range)
+    const uint32_t nv = (uint32_t)(b - a);
+    for (uint32_t i = threadIdx.x; i <= nv; i += 256) {
+        const uint64_t t = a + i - 1;
+        s_val[i] = (i == 0 && a == lo) ? __longlong_as_double(0x7ff8000000000000ll) : ord_value(S[t], J.dtype);
+    }
     for (uint32_t k = threadIdx.x; k < L; k += 256) {
         s_best[k] = 0;
         s_first[k] = 0;
     }
-    const uint64_t* S = sorted + J.sample_off;
     const Root R = root_of(S, lo, hi, J.dtype, L);
     __syncthreads();
-    // each lane walks 16 consecutive words; a run's length is counted in
-    // place and only a run reaching past the lane's range is searched for
-    constexpr uint32_t kPer = kSampleBlock / 256;
-    const uint64_t r0 = a + (uint64_t)threadIdx.x * kPer;
-    const uint64_t r1 = min(r0 + kPer, b);
-    for (uint64_t t = r0; t < r1;) {
-        const double x = ord_value(S[t], J.dtype);
-        uint64_t e = t + 1;
-        while (e < r1 && ord_value(S[e], J.dtype) == x)
+    const uint32_t r0 = threadIdx.x * kPer;
+    const uint32_t r1 = min(r0 + kPer, nv);
+    for (uint32_t i = r0; i < r1;) {
+        const double x = s_val[i + 1];
+        uint32_t e = i + 1;
+        while (e < r1 && s_val[e + 1] == x)
             ++e;
-        const bool start = t == lo || ord_value(S[t - 1], J.dtype) != x;
-        if (start) {
+        if (!(s_val[i] == x)) {                        // a run starts here (NaN before lo)
+            uint64_t end = a + e;
             if (e == r1)
-                e = value_upper(S, r1, hi, x, J.dtype);
+                end = value_upper(S, a + r1, hi, x, J.dtype);
             const uint32_t k = root_leaf(x, R, L);
-            const uint64_t rel = t - lo;
-            atomicMax(&s_best[k], (unsigned long long)(((e - t) << 32) | (0xffffffffull - rel)));
-            atomicMax(&s_first[k], (unsigned long long)~rel);
+            const uint64_t rel = a + i - lo, len = end - (a + i);
+            atomicMax(&s_best[k], (unsigned long long)((len << 32) | (0xffffffffull - rel)));
+            atomicMax(&s_first[k], (unsigned long long)(((0xffffffffull - rel) << 32) | len));
         }
-        t = e > r1 ? r1 : e;
+        i = e;
     }
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < L; k += 256) {
@@ -307,10 +315,9 @@ __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const u
                 kB[k] = (uint32_t)(0xffffffffull - (key & 0xffffffffull));
                 kd[k] = (uint32_t)len;
             } else {
-                const uint64_t f0 = ~firstc[J.leaf_off + k];
-                kB[k] = (uint32_t)f0;
-                kd[k] = (uint32_t)(value_upper(S, lo + f0 + 1, hi, ord_value(S[lo + f0], J.dtype), J.dtype) -
-                                   (lo + f0));
+                const uint64_t fr = firstc[J.leaf_off + k];
+                kB[k] = (uint32_t)(0xffffffffull - (fr >> 32));
+                kd[k] = (uint32_t)(fr & 0xffffffffull);
             }
         }
         __syncthreads();
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const u
             }
             if (!knot) {
                 // empty leaf: constant at the sample count below it
-                const uint64_t nb = q != 0x7fffffff ? ~firstc[J.leaf_off + q] : mfin;
+                const uint64_t nb = q != 0x7fffffff ? 0xffffffffull - (firstc[J.leaf_off + q] >> 32) : mfin;
                 const double v = (double)nb / mf;
                 seg[2 * k] = make_double2(inf, v);
                 seg[2 * k + 1] = make_double2(0.0, v);
