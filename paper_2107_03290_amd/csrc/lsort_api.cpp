@@ -438,17 +438,17 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         TRY(ensure(C, C->skip, R.buckets, st));
         TRY(ensure(C, C->tflags, (size_t)nt * 4, st));
         // Output lists, sized by what classify can emit: a next-round task
-        // is a bucket of more than T keys; a fill bucket holds at least
+        // is a bucket of at least 2T keys; a fill bucket holds at least
         // max(T/8, 2) keys (plus one piece per kFillPiece keys); a group of
         // class c > 0 holds more than the previous class cap; a group of
-        // class 0 starts after an empty-free run of small buckets is broken
-        // by the task start, a T-key window boundary or a big / fill bucket,
-        // so there are at most 2 n/T + n/fill_min + 2 of them per task.
-        const uint64_t T1 = (uint64_t)P.base + 1;
-        const uint64_t max_tasks = std::min<uint64_t>(R.buckets, R.nkeys / T1) + 1;
+        // class 0 is a solo bucket (more than T keys) or starts where a run
+        // of small buckets is broken by the task start, a T-key window
+        // boundary or a big / fill / solo bucket, so there are at most
+        // 3 n/T + n/fill_min + 2 of them per task.
+        const uint64_t max_tasks = std::min<uint64_t>(R.buckets, R.nkeys / (2ull * P.base)) + 1;
         const uint64_t fill_min = std::max<uint64_t>(P.base / 8, 2);
         const uint64_t max_fills = std::min<uint64_t>(R.buckets, R.nkeys / fill_min) + R.nkeys / kFillPiece + 1;
-        const uint64_t g0 = 2 * (R.nkeys / P.base) + R.nkeys / fill_min + 2 * (uint64_t)nt + 2;
+        const uint64_t g0 = 3 * (R.nkeys / P.base) + R.nkeys / fill_min + 2 * (uint64_t)nt + 2;
         const uint64_t max_groups[kGroupClasses] = {std::min<uint64_t>(R.buckets, g0) + 1,
                                                     R.nkeys / (kGroupClassCap[0] + 1) + 1,
                                                     R.nkeys / (kGroupClassCap[1] + 1) + 1};

@@ -189,12 +189,13 @@ hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chun
 // -------------------------------------------------------------- classify --
 
 // Classify every bucket of a task: empty, all-equal (filled with its value,
-// never moved again), small (sorted in LDS together with its neighbours) or
-// over-full (a task of the next round).  Small buckets hold at most `thresh`
-// keys; consecutive small buckets whose starts fall into the same window of
-// `thresh` keys form one group, so a group holds fewer than 2*thresh keys.
-// Everything is decided with block-wide scans, no serial walk.
-enum : uint8_t { kEmpty = 0, kSmall = 1, kFillB = 2, kBig = 3, kLead = 0x80 };
+// never moved again), small (sorted in LDS together with its neighbours),
+// solo (more than `thresh` but fewer than 2*thresh keys: sorted in LDS as a
+// group of its own) or over-full (a task of the next round).  Small buckets
+// hold at most `thresh` keys; consecutive small buckets whose starts fall into
+// the same window of `thresh` keys form one group, so a group holds fewer than
+// 2*thresh keys.  Everything is decided with block-wide scans, no serial walk.
+enum : uint8_t { kEmpty = 0, kSmall = 1, kFillB = 2, kBig = 3, kSolo = 4, kLead = 0x80 };
 
 constexpr int32_t kNone = 0x7fffffff;
 
@@ -261,7 +262,10 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
             m = m > floor_m ? m : floor_m;
             if (lp.cap && m > lp.cap)
                 m = lp.cap > floor_m ? lp.cap : floor_m;
-            L = (uint32_t)(m < lp.leaves ? m : lp.leaves);
+            // about 8 sample keys per leaf (the knot of a repeated value
+            // needs m/L copies), at most the caller's leaves
+            const uint64_t want_l = m / 8 ? m / 8 : 1;
+            L = (uint32_t)(want_l < lp.leaves ? want_l : lp.leaves);
             my_maxl = max(my_maxl, L);
             atomicMax(&s_maxm, (unsigned long long)m);
         }
@@ -409,8 +413,10 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
             k = kEmpty;
         else if (lo == hi && sz >= fill_min)
             k = kFillB;
-        else if (lo != hi && sz > thresh)
+        else if (lo != hi && sz >= 2ull * thresh)
             k = kBig;
+        else if (lo != hi && sz > thresh)
+            k = kSolo;
         else
             k = kSmall;
         bst[b] = s0;
@@ -422,7 +428,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
     block_scan_op<int32_t>(prv, f, -1, MaxI32(), ws_i);      // prv[b]: last non-empty bucket before b
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
         const uint8_t k = kind[b];
-        bool lead = false;
+        bool lead = k == kSolo;
         if (k == kSmall) {
             const int32_t p = prv[b];
             lead = p < 0 || kind[p] != kSmall || bst[p] / thresh != bst[b] / thresh;
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
             atomicAdd(&s_fkeys, (unsigned long long)sz);
             atomicAdd(&s_nfb, 1u);
         }
-        if (k == kSmall)
+        if (k == kSmall || k == kSolo)
             atomicAdd(&s_gkeys, (unsigned long long)sz);
     }
     __syncthreads();
@@ -446,7 +452,8 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
         const int32_t p = prv[b];
         const uint8_t k = kind[b];
-        const bool lead = k == kSmall && (p < 0 || kind[p] != kSmall || bst[p] / thresh != bst[b] / thresh);
+        const bool lead = k == kSolo ||
+                          (k == kSmall && (p < 0 || kind[p] != kSmall || bst[p] / thresh != bst[b] / thresh));
         prv[b] = lead ? 1 : 0;     // temporary: leader flag
     }
     __syncthreads();
