@@ -268,16 +268,46 @@ __device__ void lds_bitonic(uint64_t* s, uint32_t logN)
 
 // ------------------------------------------------------------ block scans --
 
-// Exclusive scan of a[0..n) (LDS, u32) in place; returns the total.
-// wsum: LDS scratch of blockDim/64 + 1 entries.
-__device__ inline uint32_t block_scan_u32(uint32_t* a, uint32_t n, uint32_t* wsum)
+// Exclusive prefix of the per-wave totals wsum[0..nw) in place, with the
+// grand total in wsum[nw]; done by wave 0 with shuffles.  Call between two
+// barriers of the whole block.
+template <typename T, typename Op>
+__device__ __forceinline__ void wave_totals_scan(T* wsum, uint32_t nw, T ident, Op op)
+{
+    if (threadIdx.x < 64) {
+        const uint32_t lane = threadIdx.x;
+        T v = lane < nw ? wsum[lane] : ident;
+#pragma unroll
+        for (uint32_t d = 1; d < 16; d <<= 1) {
+            const T y = __shfl_up(v, d, 64);
+            if (lane >= d)
+                v = op(y, v);
+        }
+        T ex = __shfl_up(v, 1, 64);
+        if (lane == 0)
+            ex = ident;
+        if (lane < nw)
+            wsum[lane] = ex;
+        if (lane + 1 == nw)
+            wsum[nw] = v;
+    }
+}
+
+struct AddU32 {
+    __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; }
+};
+
+// Exclusive scan of in[0..n) (LDS, u32) into out[0..n) (may be the same
+// array); returns the total.  wsum: LDS scratch of blockDim/64 + 1 entries;
+// at most 16 waves.
+__device__ inline uint32_t block_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* wsum)
 {
     const uint32_t nt = blockDim.x;
     const uint32_t per = (n + nt - 1) / nt;
     const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
     uint32_t s = 0;
     for (uint32_t i = lo; i < hi; ++i)
-        s += a[i];
+        s += in[i];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     uint32_t x = s;
 #pragma unroll
@@ -289,25 +319,22 @@ __device__ inline uint32_t block_scan_u32(uint32_t* a, uint32_t n, uint32_t* wsu
     if (lane == 63)
         wsum[wave] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (uint32_t w = 0; w < nt / 64; ++w) {
-            uint32_t v = wsum[w];
-            wsum[w] = run;
-            run += v;
-        }
-        wsum[nt / 64] = run;
-    }
+    wave_totals_scan<uint32_t>(wsum, nt / 64, 0u, AddU32());
     __syncthreads();
     uint32_t base = wsum[wave] + x - s;
     for (uint32_t i = lo; i < hi; ++i) {
-        uint32_t v = a[i];
-        a[i] = base;
+        uint32_t v = in[i];
+        out[i] = base;
         base += v;
     }
     uint32_t total = wsum[nt / 64];
     __syncthreads();
     return total;
+}
+
+__device__ inline uint32_t block_scan_u32(uint32_t* a, uint32_t n, uint32_t* wsum)
+{
+    return block_scan_u32(a, a, n, wsum);
 }
 
 // Generic exclusive block scan (LDS, in place) with an associative operator;
@@ -336,15 +363,7 @@ __device__ T block_scan_op(T* a, uint32_t n, T ident, Op op, T* wsum)
     if (lane == 63)
         wsum[wave] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        T run = ident;
-        for (uint32_t w = 0; w < nt / 64; ++w) {
-            T v = wsum[w];
-            wsum[w] = run;
-            run = op(run, v);
-        }
-        wsum[nt / 64] = run;
-    }
+    wave_totals_scan<T>(wsum, nt / 64, ident, op);
     __syncthreads();
     T base = op(wsum[wave], ex);
     for (uint32_t i = lo; i < hi; ++i) {

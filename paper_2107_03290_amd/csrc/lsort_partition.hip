@@ -652,10 +652,7 @@ __device__ __forceinline__ void scatter_body(const Task& T, const uint64_t* src,
             }
         }
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < f; b += kScatterThreads)
-            tstart[b] = tcnt[b];
-        __syncthreads();
-        const uint32_t ntile = block_scan_u32(tstart, f, wsum);
+        const uint32_t ntile = block_scan_u32(tcnt, tstart, f, wsum);
 #pragma unroll
         for (uint32_t u = 0; u < KPT; ++u) {
             if (bk[u] != ~0u) {
