@@ -56,6 +56,11 @@ typedef enum { LS_F64 = 1, LS_U64 = 2 } ls_dtype;
 #define LS_FLAG_SYNC           0x2u   /* wait for the stream before returning */
 #define LS_FLAG_NONMONOTONE    0x4u   /* test hook: perturb predictions so buckets overlap; the touch-up must repair */
 #define LS_FLAG_PROFILE        0x8u   /* time each kernel class with HIP events (read with ls_last_profile) */
+#define LS_FLAG_GRAPH          0x10u  /* run a batch of at most 2^22 keys and 2^16 arrays as one replay of a HIP
+                                         graph captured for its size class (keys and arrays rounded up to powers
+                                         of two); the first batch of a class captures it.  Results are the same
+                                         as without the flag.  Ignored with LS_FLAG_PROFILE or
+                                         LS_FLAG_DEBUG_TOUCHUP and for larger batches. */
 
 /* Tuning parameters (Sec. 6.1 gives f = 1000, c = 100, L = 1000, 1% sample).
  * Zero fields take the library defaults.  None of them changes the result. */
@@ -196,7 +201,8 @@ typedef struct ls_server ls_server;
  * they need (keys already resident + the library's scratch) stays within
  * hbm_budget_bytes, batches the admitted ones into segmented sorts, and
  * keeps up to max_inflight batches in flight on separate streams.  p may be
- * NULL. */
+ * NULL: the defaults with LS_FLAG_GRAPH (batches of up to 2^22 keys run as
+ * graph replays). */
 ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
                            uint32_t max_inflight, const ls_params* p);
 

@@ -25,6 +25,7 @@ FLAG_DEBUG_TOUCHUP = 0x1
 FLAG_SYNC = 0x2
 FLAG_NONMONOTONE = 0x4
 FLAG_PROFILE = 0x8
+FLAG_GRAPH = 0x10
 
 KERNEL_CLASSES = ("train", "hist", "scan", "classify", "scatter", "base", "fill", "touchup")
 

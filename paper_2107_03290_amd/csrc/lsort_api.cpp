@@ -62,6 +62,15 @@ uint64_t sample_size(uint64_t n, double rate, uint64_t cap)
     return m;
 }
 
+// A captured replay of one batch size class (keys, arrays), valid while no
+// buffer it uses has been reallocated (gen).
+struct GraphEntry {
+    uint64_t keys, arrays, gen;
+    Params P;
+    hipGraphExec_t exec;
+    void* list0;          // the task list the replay uploads round 0 into and ends with
+};
+
 uint32_t group_class(uint32_t n)
 {
     return n <= kGroupClassCap[0] ? 0u : (n <= kGroupClassCap[1] ? 1u : 2u);
@@ -87,6 +96,11 @@ struct ls_ctx {
     double prof_ms[8] = {0}, prof_launch[8] = {0}, prof_bytes[8] = {0};
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
+    // graph mode
+    uint64_t gen = 0;                    // bumped whenever a buffer is reallocated
+    PinBuf gstage;                       // staging of the replays' uploads
+    hipStream_t cap_stream = nullptr;    // capture only; replays run on the caller's stream
+    std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -131,6 +145,7 @@ ls_status ensure(ls_ctx* C, DevBuf& b, size_t bytes, hipStream_t st, size_t keep
         HIPCHECK(C, hipFree(b.p));
     b.p = np;
     b.cap = nb;
+    ++C->gen;
     return LS_OK;
 }
 
@@ -150,6 +165,7 @@ ls_status ensure_pinned(ls_ctx* C, PinBuf& b, size_t bytes, hipStream_t st)
         return fail(C, LS_ERR_NOMEM, "pinned host allocation failed");
     }
     b.cap = nb;
+    ++C->gen;
     return LS_OK;
 }
 
@@ -307,9 +323,9 @@ ls_status train(ls_ctx* C, const DevBuf& jobs, uint32_t njobs, uint32_t blocks, 
     }
     if (prof)
         prof->begin(0);
-    HIPCHECK(C, launch_train((const ModelJob*)jobs.p, njobs, blocks, max_sample, (uint64_t*)C->sample.p,
+    HIPCHECK(C, launch_train((const ModelJob*)jobs.p, njobs, blocks, samples, max_sample, (uint64_t*)C->sample.p,
                              (uint64_t*)C->sample2.p, (uint64_t*)C->tbest.p, (uint64_t*)C->tfirst.p,
-                             (double*)C->models.p, st));
+                             (double*)C->models.p, nullptr, st));
     if (prof)
         prof->end((double)samples * 16.0);
     return LS_OK;
@@ -330,37 +346,29 @@ ls_status wait_ctl(ls_ctx* C, hipStream_t st)
     return LS_OK;
 }
 
-// The whole pipeline for a batch of arrays.  msd_only: partition on the
-// order-preserving bits alone (the touch-up repair path).
-ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, bool msd_only)
-{
-    uint64_t total = 0;
-    for (auto& a : arrays)
-        total += a.n;
-    TRY(ensure(C, C->scratch, std::max<uint64_t>(total, 1) * 8, st));
-    {
-        uint64_t off = 0;
-        for (auto& a : arrays) {
-            a.scratch = (uint64_t*)C->scratch.p + off;
-            off += a.n;
-        }
-    }
-    TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
-
-    // Round-0 work: small arrays go straight to the base case, large ones
-    // get a global model (level 0 of Alg. 2).
+// Round-0 work of a batch: small arrays go straight to the base case, large
+// ones get a global model (level 0 of Alg. 2), or an MSD split of the key
+// bits in the repair pass.
+struct Batch {
     std::vector<Group> groups0[kGroupClasses];
     std::vector<Task> tasks;
     Trainer tr;
+    uint64_t total = 0, group0_keys = 0;
+};
+
+void prepare(std::vector<Array>& arrays, void* scratch, const Params& P, bool msd_only, Batch& B)
+{
     const uint32_t lf = 31u - (uint32_t)__builtin_clz(P.fanout);
-    uint64_t group0_keys = 0;
+    uint64_t off = 0;
     for (uint32_t i = 0; i < arrays.size(); ++i) {
-        const Array& a = arrays[i];
+        Array& a = arrays[i];
+        a.scratch = (uint64_t*)scratch + off;
+        off += a.n;
         if (a.n <= 1)
             continue;
         if (a.n <= 2ull * P.base) {
-            groups0[group_class((uint32_t)a.n)].push_back(Group{a.keys, a.keys, 0, (uint32_t)a.n, a.dtype});
-            group0_keys += a.n;
+            B.groups0[group_class((uint32_t)a.n)].push_back(Group{a.keys, a.keys, 0, (uint32_t)a.n, a.dtype});
+            B.group0_keys += a.n;
             continue;
         }
         Task t{};
@@ -378,57 +386,48 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
             t.fanout = child_fanout(a.n, P.base, P.fanout);
             t.scale = (double)t.fanout;
             t.leaves = P.leaves;
-            t.model = tr.add(a.keys, a.n, sample_size(a.n, P.rate, P.cap), P.seed, P.leaves, a.dtype);
+            t.model = B.tr.add(a.keys, a.n, sample_size(a.n, P.rate, P.cap), P.seed, P.leaves, a.dtype);
         }
-        tasks.push_back(t);
+        B.tasks.push_back(t);
     }
-    const uint64_t global_models = tr.models;
-    Prof prof{C, st, (P.flags & LS_FLAG_PROFILE) != 0, {}};
+    B.total = off;
+}
 
-    std::memset(C->h_ctl_init, 0, sizeof(RoundCtl));
-    C->h_ctl_init->ntasks = (uint32_t)tasks.size();
-    for (uint32_t c = 0; c < kGroupClasses; ++c) {
-        C->h_ctl_init->ngroups[c] = (uint32_t)groups0[c].size();
-        TRY(ensure(C, C->groups[c], std::max<size_t>(groups0[c].size(), 1) * sizeof(Group), st));
-        TRY(upload(C, C->pin_groups[c], C->groups[c], groups0[c], st));
-    }
-    HIPCHECK(C, hipMemcpyAsync(C->ctl.p, C->h_ctl_init, sizeof(RoundCtl), hipMemcpyHostToDevice, st));
-    TRY(ensure(C, C->next, std::max<size_t>(tasks.size(), 1) * sizeof(Task), st));
-    TRY(ensure(C, C->ljobs, std::max<size_t>(tasks.size(), 1) * sizeof(ModelJob), st));
-    TRY(upload(C, C->pin_tasks, C->next, tasks, st));
-    if (!tr.jobs.empty()) {
-        TRY(ensure(C, C->gjobs, tr.jobs.size() * sizeof(ModelJob), st));
-        TRY(upload(C, C->pin_jobs, C->gjobs, tr.jobs, st));
-        TRY(train(C, C->gjobs, (uint32_t)tr.jobs.size(), tr.blocks, tr.samples, tr.leaves, tr.max_sample, 0,
-                  tr.models, st, &prof));
-    }
+constexpr uint64_t kUnbounded = ~0ull;
+
+LayoutParams layout_params(const Params& P, uint64_t model_base)
+{
     LayoutParams lp;
+    std::memset(&lp, 0, sizeof lp);
     lp.fanout = P.fanout;
     lp.leaves = P.leaves;
     lp.tile = P.tile;
-    lp.pad = 0;
     lp.rate = P.rate;
     lp.cap = P.cap;
     lp.seed = P.seed;
-    lp.model_base = global_models;
-    if (!tasks.empty()) {
-        HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp, (RoundCtl*)C->ctl.p, C->d_h_ctl,
-                                  st));
-        TRY(wait_ctl(C, st));
-    } else {
-        TRY(read_ctl(C, st));
-    }
-    prof.collect();
+    lp.model_base = model_base;
+    lp.cap_tasks = lp.cap_fills = kUnbounded;
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        lp.cap_groups[c] = kUnbounded;
+    lp.cap_keys = lp.cap_chunks = lp.cap_buckets = lp.cap_entries = kUnbounded;
+    lp.cap_samples = lp.cap_blocks = lp.cap_leafs = lp.cap_models = kUnbounded;
+    return lp;
+}
 
-    uint64_t rounds = 0, ntasks_total = 0;
-    uint32_t max_level = 0;
-    const uint32_t flags = msd_only ? 0u : (P.flags & LS_FLAG_NONMONOTONE);
+ls_status check_overflow(ls_ctx* C)
+{
+    if (C->h_ctl->overflow)
+        return fail(C, LS_ERR_HIP, "a partition round exceeded its buffers (internal size bound)");
+    return LS_OK;
+}
+
+// Partition rounds, driven from the host: each round's launches are sized
+// from the control block the previous layout published.
+ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams lp, uint32_t flags, Prof& prof)
+{
     while (C->h_ctl->ntasks) {
         const RoundCtl R = *C->h_ctl;
         const uint32_t nt = R.ntasks;
-        ++rounds;
-        ntasks_total += nt;
-        max_level = std::max(max_level, R.max_level);
         std::swap(C->tasks, C->next);
         TRY(ensure(C, C->cnt, R.entries * 4, st));
         TRY(ensure(C, C->pos, R.entries * 8, st));
@@ -458,33 +457,36 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
             TRY(ensure(C, C->groups[c], ((size_t)R.ngroups[c] + max_groups[c]) * sizeof(Group), st,
                        (size_t)R.ngroups[c] * sizeof(Group)));
             gl.g[c] = (Group*)C->groups[c].p;
+            lp.cap_groups[c] = C->groups[c].cap / sizeof(Group);
         }
         TRY(ensure(C, C->fills, ((size_t)R.nfill + max_fills) * sizeof(Fill), st, (size_t)R.nfill * sizeof(Fill)));
+        lp.cap_fills = C->fills.cap / sizeof(Fill);
         // local models of this round's tasks (jobs written by the last layout)
-        TRY(train(C, C->ljobs, R.njobs, R.blocks, R.samples, R.leafs, R.max_sample, global_models, R.models, st,
+        TRY(train(C, C->ljobs, R.njobs, R.blocks, R.samples, R.leafs, R.max_sample, lp.model_base, R.models, st,
                   &prof));
         TRY(ensure(C, C->ljobs, max_tasks * sizeof(ModelJob), st));
-        HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, R.buckets, (RoundCtl*)C->ctl.p, st));
+        lp.cap_tasks = std::min(C->next.cap / sizeof(Task), C->ljobs.cap / sizeof(ModelJob));
+        HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, R.buckets, (RoundCtl*)C->ctl.p, false, st));
         prof.begin(1);
         HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
                                 (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, (uint16_t*)C->ids.p, R.max_fanout,
-                                R.max_leaves, flags, st));
+                                R.max_leaves, flags, nullptr, st));
         prof.end((double)R.nkeys * 10.0);
         prof.begin(2);
         HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, R.entries, (uint64_t*)C->scantmp.p,
-                                st));
+                                nullptr, st));
         prof.end((double)R.entries * 16.0);
         prof.begin(3);
         HIPCHECK(C, launch_classify((const Task*)C->tasks.p, nt, (const uint64_t*)C->pos.p,
                                     (const uint64_t*)C->bstat.p, P.base, P.fanout, (Task*)C->next.p, gl,
                                     (Fill*)C->fills.p, (uint8_t*)C->skip.p, (uint32_t*)C->tflags.p,
                                     (RoundCtl*)C->ctl.p, R.max_fanout, (ModelJob*)C->ljobs.p, lp, C->d_h_ctl,
-                                    st));
+                                    nullptr, st));
         prof.end((double)R.buckets * 32.0);
         prof.begin(4);
         HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const uint16_t*)C->ids.p,
                                    (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
-                                   (const uint32_t*)C->tflags.p, P.tile, R.max_fanout, st));
+                                   (const uint32_t*)C->tflags.p, P.tile, R.max_fanout, nullptr, st));
         prof.end(0.0);
         TRY(wait_ctl(C, st));
         if (prof.on && !prof.recs.empty()) {
@@ -495,39 +497,55 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
             prof.recs.back().bytes = 10.0 * moved + 8.0 * kept;
         }
         prof.collect();
+        TRY(check_overflow(C));
     }
+    return LS_OK;
+}
 
-    // finish: LDS base case, all-equal fills, touch-up
+// Finish: LDS base case, all-equal fills, touch-up; reads the final control
+// block back.
+ls_status finish_eager(ls_ctx* C, hipStream_t st, const Params& P, Prof& prof, uint64_t group0_keys)
+{
     const RoundCtl F = *C->h_ctl;
     GroupLists gl;
     for (uint32_t c = 0; c < kGroupClasses; ++c)
         gl.g[c] = (Group*)C->groups[c].p;
     const double gkeys = (double)F.group_keys + (double)group0_keys;
     prof.begin(5);
-    HIPCHECK(C, launch_base(gl, F.ngroups, st));
+    HIPCHECK(C, launch_base(gl, F.ngroups, nullptr, st));
     prof.end(16.0 * gkeys);
     prof.begin(6);
-    HIPCHECK(C, launch_fill((const Fill*)C->fills.p, F.nfill, st));
+    HIPCHECK(C, launch_fill((const Fill*)C->fills.p, F.nfill, nullptr, st));
     prof.end(8.0 * (double)F.fillkeys);
     prof.begin(7);
     HIPCHECK(C, launch_touchup(gl, F.ngroups, (const Fill*)C->fills.p, F.nfill,
-                               (P.flags & LS_FLAG_DEBUG_TOUCHUP) ? 1 : 0, (RoundCtl*)C->ctl.p, st));
+                               (P.flags & LS_FLAG_DEBUG_TOUCHUP) ? 1 : 0, (RoundCtl*)C->ctl.p, false, st));
     const uint64_t ngroups = (uint64_t)F.ngroups[0] + F.ngroups[1] + F.ngroups[2];
     prof.end(16.0 * (double)(ngroups + F.nfill));
     TRY(read_ctl(C, st));
     prof.collect();
+    return LS_OK;
+}
+
+ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, bool msd_only);
+
+// Statistics of the finished sort, and the touch-up repair when a seam was
+// out of order.
+ls_status conclude(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, bool msd_only)
+{
+    TRY(check_overflow(C));
     const RoundCtl fin = *C->h_ctl;
-    C->stats[0] = rounds;
-    C->stats[1] = ntasks_total;
-    C->stats[2] = ngroups;
+    C->stats[0] = fin.rounds;
+    C->stats[1] = fin.tasks_total;
+    C->stats[2] = (uint64_t)fin.ngroups[0] + fin.ngroups[1] + fin.ngroups[2];
     C->stats[3] = fin.nfillbuckets;
     C->stats[4] = fin.fillkeys;
     C->stats[5] = fin.fallbacks;
     C->stats[6] = fin.violations;
-    C->stats[7] = max_level;
+    C->stats[7] = fin.deepest;
     if (fin.fallbacks)
         C->dev_status |= LS_DEV_FALLBACK;
-    if (max_level > 1)
+    if (fin.deepest > 1)
         C->dev_status |= LS_DEV_DEEP;
     if (fin.violations) {
         if (msd_only)
@@ -541,6 +559,360 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         C->dev_status |= LS_DEV_SEAM_REPAIRED;
     }
     return LS_OK;
+}
+
+// ------------------------------------------------------------ graph mode --
+//
+// A batch of at most kGraphMaxKeys keys can run as one replay of a HIP graph
+// captured for its size class (keys and arrays rounded up to powers of two):
+// uploads of the round-0 lists, global training, layout, kGraphRounds
+// partition rounds and the finish.  Every buffer is sized from bounds on what
+// a round of the class can produce, the kernels are launched with grids for
+// those bounds and read their real sizes from the control block, and rounds
+// past the last task run nothing.  A batch that needs more rounds continues
+// on the host-driven path from the state the replay left.
+
+constexpr uint64_t kGraphMinKeys = 1ull << 16;
+constexpr uint64_t kGraphMaxKeys = 1ull << 22;
+constexpr uint64_t kGraphMinArrays = 64;
+constexpr uint64_t kGraphMaxArrays = 1ull << 16;
+constexpr uint32_t kGraphRounds = 4;   // even: the next-round tasks end in C->next
+static_assert(kGraphRounds % 2 == 0, "the task lists alternate between rounds");
+
+uint64_t pow2_ge(uint64_t x)
+{
+    uint64_t p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+// Upper bounds for a batch of at most `keys` keys in at most `arrays` arrays.
+struct Caps {
+    uint64_t keys, arrays;
+    // round 0
+    uint64_t tasks0, gsamples, gblocks, gleafs, gmodels, gmax_sample;
+    // one partition round
+    uint64_t tasks, chunks, buckets, entries, samples, blocks, leafs, models, max_sample;
+    // over the whole replay
+    uint64_t groups[kGroupClasses], fills;
+    // pinned staging: control block, tasks, jobs, groups of each class
+    size_t off_tasks, off_jobs, off_groups[kGroupClasses], stage_bytes;
+};
+
+Caps graph_caps(uint64_t keys, uint64_t arrays, const Params& P)
+{
+    Caps K{};
+    const uint64_t N = keys, T = P.base;
+    K.keys = N;
+    K.arrays = arrays;
+    const uint64_t rate_n = (uint64_t)std::ceil(P.rate * (double)N);
+    // round 0: one task and one global model per array of more than 2T keys
+    K.tasks0 = std::min<uint64_t>(arrays, N / (2 * T + 1)) + 1;
+    K.gsamples = std::min<uint64_t>(N, rate_n + K.tasks0);
+    K.gblocks = K.gsamples / kSampleBlock + K.tasks0 + 1;
+    K.gleafs = K.tasks0 * P.leaves;
+    K.gmodels = K.tasks0 * model_doubles(P.leaves);
+    K.gmax_sample = std::max<uint64_t>(1, P.cap ? std::min<uint64_t>(rate_n, P.cap) : rate_n);
+    // a round: tasks are arrays or buckets of at least 2T keys; a task of n
+    // keys has at most 66 + 128 n / T buckets (child_fanout) in at most
+    // n / chunk + 1 chunks, with chunk >= keys / kTargetChunks; a local
+    // sample takes ceil(rate n) or up to kLocalMinSample keys, and about one
+    // leaf per 8 sample keys
+    K.tasks = std::max<uint64_t>(K.tasks0, N / (2 * T) + 1);
+    K.chunks = kTargetChunks + K.tasks;
+    K.buckets = std::min<uint64_t>((uint64_t)P.fanout * K.tasks, 66 * K.tasks + 128 * N / T + 128);
+    K.entries = (uint64_t)P.fanout * kTargetChunks + K.buckets;
+    K.samples = std::min<uint64_t>(N, rate_n + (kLocalMinSample + 1) * K.tasks);
+    K.blocks = K.samples / kSampleBlock + K.tasks + 1;
+    K.leafs = std::min<uint64_t>((uint64_t)P.leaves * K.tasks, K.samples / 8 + K.tasks);
+    K.models = 8 * K.leafs + 16 * K.tasks;
+    K.max_sample = std::min<uint64_t>(N, std::max<uint64_t>(K.gmax_sample, kLocalMinSample));
+    // lists: the per-round bounds of rounds_eager, over every round, plus
+    // the small arrays of round 0
+    const uint64_t fill_min = std::max<uint64_t>(P.base / 8, 2);
+    const uint64_t g0 = std::min<uint64_t>(K.buckets, 3 * (N / T) + N / fill_min + 2 * K.tasks + 2) + 1;
+    K.groups[0] = arrays + kGraphRounds * g0;
+    K.groups[1] = arrays + kGraphRounds * (N / (kGroupClassCap[0] + 1) + 1);
+    K.groups[2] = arrays + kGraphRounds * (N / (kGroupClassCap[1] + 1) + 1);
+    K.fills = kGraphRounds * (std::min<uint64_t>(K.buckets, N / fill_min) + N / kFillPiece + 1);
+    size_t off = (sizeof(RoundCtl) + 255) & ~(size_t)255;
+    K.off_tasks = off;
+    off += K.tasks0 * sizeof(Task);
+    K.off_jobs = off;
+    off += K.tasks0 * sizeof(ModelJob);
+    for (uint32_t c = 0; c < kGroupClasses; ++c) {
+        K.off_groups[c] = off;
+        off += arrays * sizeof(Group);
+    }
+    K.stage_bytes = off;
+    return K;
+}
+
+bool same_params(const Params& a, const Params& b)
+{
+    return a.fanout == b.fanout && a.leaves == b.leaves && a.tile == b.tile && a.base == b.base &&
+           a.flags == b.flags && a.rate == b.rate && a.cap == b.cap && a.seed == b.seed;
+}
+
+// Size every buffer the replay touches for the class.
+ls_status size_for_graph(ls_ctx* C, const Caps& K, hipStream_t st)
+{
+    TRY(ensure(C, C->scratch, K.keys * 8, st));
+    TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
+    TRY(ensure(C, C->next, K.tasks * sizeof(Task), st));
+    TRY(ensure(C, C->tasks, K.tasks * sizeof(Task), st));
+    TRY(ensure(C, C->gjobs, K.tasks0 * sizeof(ModelJob), st));
+    TRY(ensure(C, C->ljobs, K.tasks * sizeof(ModelJob), st));
+    TRY(ensure(C, C->models, (K.gmodels + K.models) * sizeof(double), st));
+    TRY(ensure(C, C->sample, std::max(K.gsamples, K.samples) * 8, st));
+    TRY(ensure(C, C->sample2, std::max(K.gsamples, K.samples) * 8, st));
+    DevBuf* tabs[2] = {&C->tbest, &C->tfirst};
+    for (DevBuf* t : tabs) {
+        const void* before = t->p;
+        TRY(ensure(C, *t, std::max(K.gleafs, K.leafs) * 8, st));
+        if (t->p != before)
+            HIPCHECK(C, hipMemsetAsync(t->p, 0, t->cap, st));
+    }
+    TRY(ensure(C, C->cnt, K.entries * 4, st));
+    TRY(ensure(C, C->pos, K.entries * 8, st));
+    TRY(ensure(C, C->scantmp, scan_tmp_entries(K.entries) * 8, st));
+    TRY(ensure(C, C->bstat, K.buckets * 16, st));
+    TRY(ensure(C, C->ids, K.keys * 2, st));
+    TRY(ensure(C, C->skip, K.buckets, st));
+    TRY(ensure(C, C->tflags, K.tasks * 4, st));
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        TRY(ensure(C, C->groups[c], K.groups[c] * sizeof(Group), st));
+    TRY(ensure(C, C->fills, K.fills * sizeof(Fill), st));
+    TRY(ensure_pinned(C, C->gstage, K.stage_bytes, st));
+    return LS_OK;
+}
+
+LayoutParams graph_layout_params(ls_ctx* C, const Caps& K, const Params& P)
+{
+    LayoutParams lp = layout_params(P, K.gmodels);
+    lp.cap_tasks = K.tasks;
+    lp.cap_fills = C->fills.cap / sizeof(Fill);
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        lp.cap_groups[c] = C->groups[c].cap / sizeof(Group);
+    lp.cap_keys = K.keys;
+    lp.cap_chunks = K.chunks;
+    lp.cap_buckets = K.buckets;
+    lp.cap_entries = K.entries;
+    lp.cap_samples = K.samples;
+    lp.cap_blocks = K.blocks;
+    lp.cap_leafs = K.leafs;
+    lp.cap_models = K.models;
+    return lp;
+}
+
+// The launches of one replay, recorded on the capture stream.
+ls_status record_graph(ls_ctx* C, const Caps& K, const Params& P, hipStream_t cs)
+{
+    RoundCtl* ctl = (RoundCtl*)C->ctl.p;
+    const LiveCounts* live = &ctl->cur;
+    const char* sp = (const char*)C->gstage.p;
+    HIPCHECK(C, hipMemcpyAsync(ctl, sp, sizeof(RoundCtl), hipMemcpyHostToDevice, cs));
+    HIPCHECK(C, hipMemcpyAsync(C->next.p, sp + K.off_tasks, K.tasks0 * sizeof(Task), hipMemcpyHostToDevice, cs));
+    HIPCHECK(C, hipMemcpyAsync(C->gjobs.p, sp + K.off_jobs, K.tasks0 * sizeof(ModelJob), hipMemcpyHostToDevice, cs));
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        HIPCHECK(C, hipMemcpyAsync(C->groups[c].p, sp + K.off_groups[c], K.arrays * sizeof(Group),
+                                   hipMemcpyHostToDevice, cs));
+    uint64_t* sample = (uint64_t*)C->sample.p;
+    uint64_t* sample2 = (uint64_t*)C->sample2.p;
+    uint64_t* tbest = (uint64_t*)C->tbest.p;
+    uint64_t* tfirst = (uint64_t*)C->tfirst.p;
+    double* models = (double*)C->models.p;
+    // global models: the host put their counts in ctl->cur
+    HIPCHECK(C, launch_train((const ModelJob*)C->gjobs.p, (uint32_t)K.tasks0, (uint32_t)K.gblocks, K.gsamples,
+                             K.gmax_sample, sample, sample2, tbest, tfirst, models, live, cs));
+    const LayoutParams lp = graph_layout_params(C, K, P);
+    HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp, ctl, C->d_h_ctl, cs));
+    Task* lists[2] = {(Task*)C->next.p, (Task*)C->tasks.p};
+    GroupLists gl;
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        gl.g[c] = (Group*)C->groups[c].p;
+    const uint32_t flags = P.flags & LS_FLAG_NONMONOTONE;
+    for (uint32_t r = 0; r < kGraphRounds; ++r) {
+        Task* in = lists[r & 1];
+        Task* out = lists[(r + 1) & 1];
+        const uint32_t nt = (uint32_t)(r == 0 ? K.tasks0 : K.tasks);
+        HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, K.buckets, ctl, true, cs));
+        HIPCHECK(C, launch_train((const ModelJob*)C->ljobs.p, (uint32_t)K.tasks, (uint32_t)K.blocks, K.samples,
+                                 K.max_sample, sample, sample2, tbest, tfirst, models, live, cs));
+        HIPCHECK(C, launch_hist(in, nt, (uint32_t)K.chunks, 0, models, (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p,
+                                (uint16_t*)C->ids.p, P.fanout, P.leaves, flags, live, cs));
+        HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, K.entries, (uint64_t*)C->scantmp.p,
+                                live, cs));
+        HIPCHECK(C, launch_classify(in, nt, (const uint64_t*)C->pos.p, (const uint64_t*)C->bstat.p, P.base,
+                                    P.fanout, out, gl, (Fill*)C->fills.p, (uint8_t*)C->skip.p,
+                                    (uint32_t*)C->tflags.p, ctl, P.fanout, (ModelJob*)C->ljobs.p, lp, C->d_h_ctl,
+                                    live, cs));
+        HIPCHECK(C, launch_scatter(in, nt, (uint32_t)K.chunks, 0, (const uint16_t*)C->ids.p,
+                                   (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
+                                   (const uint32_t*)C->tflags.p, P.tile, P.fanout, live, cs));
+    }
+    uint32_t gmax[kGroupClasses];
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        gmax[c] = (uint32_t)std::min<uint64_t>(lp.cap_groups[c], 0xffffffffu);
+    const uint32_t fmax = (uint32_t)std::min<uint64_t>(lp.cap_fills, 0xffffffffu);
+    HIPCHECK(C, launch_base(gl, gmax, ctl, cs));
+    HIPCHECK(C, launch_fill((const Fill*)C->fills.p, fmax, ctl, cs));
+    HIPCHECK(C, launch_touchup(gl, gmax, (const Fill*)C->fills.p, fmax, 0, ctl, true, cs));
+    HIPCHECK(C, hipMemcpyAsync(C->h_ctl, ctl, sizeof(RoundCtl), hipMemcpyDeviceToHost, cs));
+    return LS_OK;
+}
+
+ls_status capture_graph(ls_ctx* C, const Caps& K, const Params& P, hipGraphExec_t* out)
+{
+    if (!C->cap_stream)
+        HIPCHECK(C, hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = C->cap_stream;
+    HIPCHECK(C, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    ls_status rc = record_graph(C, K, P, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc == LS_OK && e != hipSuccess)
+        rc = fail(C, LS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (rc == LS_OK) {
+        const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess)
+            rc = fail(C, LS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    if (g)
+        (void)hipGraphDestroy(g);
+    return rc;
+}
+
+void drop_graphs(ls_ctx* C, bool all)
+{
+    for (size_t i = 0; i < C->graphs.size();) {
+        if (all || C->graphs[i].gen != C->gen) {
+            (void)hipGraphExecDestroy(C->graphs[i].exec);
+            C->graphs[i] = C->graphs.back();
+            C->graphs.pop_back();
+        } else {
+            ++i;
+        }
+    }
+}
+
+bool graph_eligible(uint64_t total, size_t narrays, const Params& P)
+{
+    return (P.flags & LS_FLAG_GRAPH) && !(P.flags & (LS_FLAG_PROFILE | LS_FLAG_DEBUG_TOUCHUP)) && total > 0 &&
+           total <= kGraphMaxKeys && narrays <= kGraphMaxArrays;
+}
+
+// One batch as a replay of its class's graph (captured on first use).
+ls_status run_graph(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, Batch& B)
+{
+    const uint64_t ckeys = std::max(pow2_ge(B.total), kGraphMinKeys);
+    const uint64_t carrays = std::max(pow2_ge(arrays.size()), kGraphMinArrays);
+    const Caps K = graph_caps(ckeys, carrays, P);
+    if (B.tasks.size() > K.tasks0 || B.tr.samples > K.gsamples || B.tr.blocks > K.gblocks ||
+        B.tr.max_sample > K.gmax_sample || B.tr.leaves > K.gleafs || B.tr.models > K.gmodels)
+        return fail(C, LS_ERR_HIP, "batch exceeds the bounds of its graph class");
+    GraphEntry* G = nullptr;
+    for (auto& e : C->graphs)
+        if (e.keys == ckeys && e.arrays == carrays && e.gen == C->gen && same_params(e.P, P))
+            G = &e;
+    if (!G) {
+        TRY(size_for_graph(C, K, st));
+        drop_graphs(C, false);
+        GraphEntry e{ckeys, carrays, C->gen, P, nullptr, C->next.p};
+        TRY(capture_graph(C, K, P, &e.exec));
+        C->graphs.push_back(e);
+        G = &C->graphs.back();
+    }
+    // Host-driven rounds swap the two task lists without reallocating them,
+    // so since the capture they may have traded places: the continuation
+    // below expects the replay's last next-round list in C->next.
+    if (C->next.p != G->list0) {
+        if (C->tasks.p != G->list0)
+            return fail(C, LS_ERR_HIP, "graph task lists out of step with the context");
+        std::swap(C->tasks, C->next);
+    }
+    // the replay's uploads read the staging area
+    char* sp = (char*)C->gstage.p;
+    RoundCtl* c0 = (RoundCtl*)sp;
+    std::memset(c0, 0, sizeof(RoundCtl));
+    c0->ntasks = (uint32_t)B.tasks.size();
+    for (uint32_t c = 0; c < kGroupClasses; ++c) {
+        c0->ngroups[c] = (uint32_t)B.groups0[c].size();
+        if (!B.groups0[c].empty())
+            std::memcpy(sp + K.off_groups[c], B.groups0[c].data(), B.groups0[c].size() * sizeof(Group));
+    }
+    c0->cur.njobs = (uint32_t)B.tr.jobs.size();
+    c0->cur.blocks = B.tr.blocks;
+    c0->cur.samples = B.tr.samples;
+    c0->cur.max_sample = B.tr.max_sample;
+    if (!B.tasks.empty())
+        std::memcpy(sp + K.off_tasks, B.tasks.data(), B.tasks.size() * sizeof(Task));
+    if (!B.tr.jobs.empty())
+        std::memcpy(sp + K.off_jobs, B.tr.jobs.data(), B.tr.jobs.size() * sizeof(ModelJob));
+    HIPCHECK(C, hipGraphLaunch(G->exec, st));
+    HIPCHECK(C, hipStreamSynchronize(st));
+    TRY(check_overflow(C));
+    if (C->h_ctl->ntasks) {
+        // more rounds than the replay holds: continue from its state
+        Prof prof{C, st, false, {}};
+        TRY(rounds_eager(C, st, P, layout_params(P, K.gmodels), P.flags & LS_FLAG_NONMONOTONE, prof));
+        TRY(finish_eager(C, st, P, prof, B.group0_keys));
+    }
+    return LS_OK;
+}
+
+// The whole pipeline for a batch of arrays.  msd_only: partition on the
+// order-preserving bits alone (the touch-up repair path).
+ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, bool msd_only)
+{
+    Batch B;
+    uint64_t total = 0;
+    for (auto& a : arrays)
+        total += a.n;
+    if (!msd_only && graph_eligible(total, arrays.size(), P)) {
+        // the scratch buffer at the class size (the replay's sizing keeps it)
+        TRY(ensure(C, C->scratch, std::max(pow2_ge(total), kGraphMinKeys) * 8, st));
+        prepare(arrays, C->scratch.p, P, false, B);
+        TRY(run_graph(C, arrays, st, P, B));
+        return conclude(C, arrays, st, P, msd_only);
+    }
+    TRY(ensure(C, C->scratch, std::max<uint64_t>(total, 1) * 8, st));
+    TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
+    prepare(arrays, C->scratch.p, P, msd_only, B);
+    const uint64_t global_models = B.tr.models;
+    Prof prof{C, st, (P.flags & LS_FLAG_PROFILE) != 0, {}};
+
+    std::memset(C->h_ctl_init, 0, sizeof(RoundCtl));
+    C->h_ctl_init->ntasks = (uint32_t)B.tasks.size();
+    for (uint32_t c = 0; c < kGroupClasses; ++c) {
+        C->h_ctl_init->ngroups[c] = (uint32_t)B.groups0[c].size();
+        TRY(ensure(C, C->groups[c], std::max<size_t>(B.groups0[c].size(), 1) * sizeof(Group), st));
+        TRY(upload(C, C->pin_groups[c], C->groups[c], B.groups0[c], st));
+    }
+    HIPCHECK(C, hipMemcpyAsync(C->ctl.p, C->h_ctl_init, sizeof(RoundCtl), hipMemcpyHostToDevice, st));
+    TRY(ensure(C, C->next, std::max<size_t>(B.tasks.size(), 1) * sizeof(Task), st));
+    TRY(ensure(C, C->ljobs, std::max<size_t>(B.tasks.size(), 1) * sizeof(ModelJob), st));
+    TRY(upload(C, C->pin_tasks, C->next, B.tasks, st));
+    if (!B.tr.jobs.empty()) {
+        TRY(ensure(C, C->gjobs, B.tr.jobs.size() * sizeof(ModelJob), st));
+        TRY(upload(C, C->pin_jobs, C->gjobs, B.tr.jobs, st));
+        TRY(train(C, C->gjobs, (uint32_t)B.tr.jobs.size(), B.tr.blocks, B.tr.samples, B.tr.leaves,
+                  B.tr.max_sample, 0, B.tr.models, st, &prof));
+    }
+    const LayoutParams lp = layout_params(P, global_models);
+    if (!B.tasks.empty()) {
+        HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp, (RoundCtl*)C->ctl.p, C->d_h_ctl,
+                                  st));
+        TRY(wait_ctl(C, st));
+    } else {
+        TRY(read_ctl(C, st));
+    }
+    prof.collect();
+    const uint32_t flags = msd_only ? 0u : (P.flags & LS_FLAG_NONMONOTONE);
+    TRY(rounds_eager(C, st, P, lp, flags, prof));
+    TRY(finish_eager(C, st, P, prof, B.group0_keys));
+    return conclude(C, arrays, st, P, msd_only);
 }
 
 ls_status sort_arrays(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const ls_params* p)
@@ -630,6 +1002,11 @@ ls_status ls_destroy(ls_ctx* C)
         (void)hipHostFree(C->h_ctl_init);
     for (hipEvent_t e : C->ev_pool)
         (void)hipEventDestroy(e);
+    drop_graphs(C, true);
+    if (C->gstage.p)
+        (void)hipHostFree(C->gstage.p);
+    if (C->cap_stream)
+        (void)hipStreamDestroy(C->cap_stream);
     delete C;
     return LS_OK;
 }
@@ -974,11 +1351,11 @@ ls_status ls_stage_hist(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n,
     TRY(ensure(C, C->cnt, (size_t)fanout * t.nchunks * 4, st));
     TRY(ensure(C, C->bstat, (size_t)fanout * 16, st));
     HIPCHECK(C, hipMemcpy(C->tasks.p, &t, sizeof(Task), hipMemcpyHostToDevice));
-    HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, fanout, (RoundCtl*)C->ctl.p, st));
+    HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, fanout, (RoundCtl*)C->ctl.p, false, st));
     TRY(ensure(C, C->ids, n * 2, st));
     HIPCHECK(C, launch_hist((const Task*)C->tasks.p, 1, t.nchunks, chunk, (const double*)C->models.p,
                             (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, (uint16_t*)C->ids.p, fanout, leaves, 0,
-                            st));
+                            nullptr, st));
     HIPCHECK(C, hipDeviceSynchronize());
     std::vector<uint32_t> cnt((size_t)fanout * t.nchunks);
     std::vector<uint64_t> bs((size_t)fanout * 2);

@@ -2,6 +2,8 @@
 // fills of all-equal buckets, touch-up check of the seams between ranges.
 #include "lsort_device.h"
 
+#include <algorithm>
+
 namespace lsort {
 
 // ------------------------------------------------------------- base case --
@@ -11,50 +13,77 @@ namespace lsort {
 // groups run in small workgroups: up to 1024 keys on 64 lanes, 4096 on 256,
 // 8192 on 512.
 template <uint32_t NT>
-__global__ __launch_bounds__(NT) void k_base(const Group* groups)
+__global__ __launch_bounds__(NT) void k_base(const Group* groups, uint32_t ngroups, const RoundCtl* gctl,
+                                             uint32_t cls)
 {
+    if (gctl) {
+        if (gctl->ntasks != 0 || gctl->overflow)
+            return;
+        ngroups = gctl->ngroups[cls];
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t* s = reinterpret_cast<uint64_t*>(smem);
-    const Group G = groups[blockIdx.x];
-    const uint32_t n = G.n;
-    if (n > NT * 16u)            // never produced by classify; keeps LDS in bounds
-        return;
-    uint32_t logN = 4;
-    while ((1u << logN) < n)
-        ++logN;
-    const uint32_t N = 1u << logN;
-    for (uint32_t i = threadIdx.x; i < N; i += NT)
-        s[base_pad(i)] = i < n ? to_ord(G.src[i], G.dtype) : ~0ull;
-    __syncthreads();
-    lds_bitonic<NT>(s, logN);
-    for (uint32_t i = threadIdx.x; i < n; i += NT)
-        G.dst[i] = from_ord(s[base_pad(i)], G.dtype);
+    // one group per workgroup; a grid smaller than the list strides over it
+    for (uint32_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const Group G = groups[g];
+        const uint32_t n = G.n;
+        if (n > NT * 16u)        // never produced by classify; keeps LDS in bounds
+            continue;
+        uint32_t logN = 4;
+        while ((1u << logN) < n)
+            ++logN;
+        const uint32_t N = 1u << logN;
+        for (uint32_t i = threadIdx.x; i < N; i += NT)
+            s[base_pad(i)] = i < n ? to_ord(G.src[i], G.dtype) : ~0ull;
+        __syncthreads();
+        lds_bitonic<NT>(s, logN);
+        for (uint32_t i = threadIdx.x; i < n; i += NT)
+            G.dst[i] = from_ord(s[base_pad(i)], G.dtype);
+        __syncthreads();
+    }
 }
 
-hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, hipStream_t st)
+// Workgroups of a graph-mode launch (the list length is only known on the
+// device): a few per CU, striding over the list.
+constexpr uint32_t kPersistBase[kGroupClasses] = {2048, 1024, 512};
+constexpr uint32_t kPersistFill = 2048;
+constexpr uint32_t kPersistTouch = 1024;
+
+hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, const RoundCtl* gctl, hipStream_t st)
 {
-    if (ngroups[0])
-        k_base<64><<<ngroups[0], 64, (size_t)base_pad(kGroupClassCap[0]) * 8, st>>>(groups.g[0]);
-    if (ngroups[1])
-        k_base<256><<<ngroups[1], 256, (size_t)base_pad(kGroupClassCap[1]) * 8, st>>>(groups.g[1]);
-    if (ngroups[2])
-        k_base<512><<<ngroups[2], 512, (size_t)base_pad(kGroupClassCap[2]) * 8, st>>>(groups.g[2]);
+    uint32_t grid[kGroupClasses];
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        grid[c] = gctl ? std::min(ngroups[c], kPersistBase[c]) : ngroups[c];
+    if (grid[0])
+        k_base<64><<<grid[0], 64, (size_t)base_pad(kGroupClassCap[0]) * 8, st>>>(groups.g[0], ngroups[0], gctl, 0);
+    if (grid[1])
+        k_base<256><<<grid[1], 256, (size_t)base_pad(kGroupClassCap[1]) * 8, st>>>(groups.g[1], ngroups[1], gctl, 1);
+    if (grid[2])
+        k_base<512><<<grid[2], 512, (size_t)base_pad(kGroupClassCap[2]) * 8, st>>>(groups.g[2], ngroups[2], gctl, 2);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ fill --
 
-__global__ __launch_bounds__(256) void k_fill(const Fill* fills)
+__global__ __launch_bounds__(256) void k_fill(const Fill* fills, uint32_t nfill, const RoundCtl* gctl)
 {
-    const Fill F = fills[blockIdx.x];
-    for (uint32_t i = threadIdx.x; i < F.n; i += 256)
-        F.dst[i] = F.raw;
+    if (gctl) {
+        if (gctl->ntasks != 0 || gctl->overflow)
+            return;
+        nfill = gctl->nfill;
+    }
+    for (uint32_t f = blockIdx.x; f < nfill; f += gridDim.x) {
+        const Fill F = fills[f];
+        for (uint32_t i = threadIdx.x; i < F.n; i += 256)
+            F.dst[i] = F.raw;
+    }
 }
 
-hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, hipStream_t st)
+hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, const RoundCtl* gctl, hipStream_t st)
 {
-    if (nfill)
-        k_fill<<<nfill, 256, 0, st>>>(d_fills);
+    const uint32_t grid = gctl ? std::min(nfill, kPersistFill) : nfill;
+    if (grid)
+        k_fill<<<grid, 256, 0, st>>>(d_fills, nfill, gctl);
     return hipGetLastError();
 }
 
@@ -70,30 +99,42 @@ struct RangeLists {
     uint32_t nfill;
 };
 
-__global__ __launch_bounds__(256) void k_touchup(RangeLists R, RoundCtl* ctl)
+__global__ __launch_bounds__(256) void k_touchup(RangeLists R, RoundCtl* ctl, bool graph)
 {
-    uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    const uint64_t* p = nullptr;
-    uint64_t start = 0;
-    uint32_t dt = 0;
-    for (uint32_t c = 0; c < kGroupClasses && !p; ++c) {
-        if (i < R.ng[c]) {
-            p = R.g[c][i].dst;
-            start = R.g[c][i].start;
-            dt = R.g[c][i].dtype;
-        } else {
-            i -= R.ng[c];
-        }
-    }
-    if (!p) {
-        if (i >= R.nfill)
+    if (graph) {
+        if (ctl->ntasks != 0 || ctl->overflow)
             return;
-        p = R.fills[i].dst;
-        start = R.fills[i].start;
-        dt = R.fills[i].dtype;
+        for (uint32_t c = 0; c < kGroupClasses; ++c)
+            R.ng[c] = ctl->ngroups[c];
+        R.nfill = ctl->nfill;
     }
-    if (start > 0 && to_ord(p[-1], dt) > to_ord(p[0], dt))
-        atomicAdd(&ctl->violations, 1u);
+    uint64_t items = R.nfill;
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        items += R.ng[c];
+    uint32_t bad = 0;
+    for (uint64_t it = (uint64_t)blockIdx.x * 256 + threadIdx.x; it < items; it += (uint64_t)gridDim.x * 256) {
+        uint64_t i = it;
+        const uint64_t* p = nullptr;
+        uint64_t start = 0;
+        uint32_t dt = 0;
+        for (uint32_t c = 0; c < kGroupClasses && !p; ++c) {
+            if (i < R.ng[c]) {
+                p = R.g[c][i].dst;
+                start = R.g[c][i].start;
+                dt = R.g[c][i].dtype;
+            } else {
+                i -= R.ng[c];
+            }
+        }
+        if (!p) {
+            p = R.fills[i].dst;
+            start = R.fills[i].start;
+            dt = R.fills[i].dtype;
+        }
+        bad += start > 0 && to_ord(p[-1], dt) > to_ord(p[0], dt);
+    }
+    if (bad)
+        atomicAdd(&ctl->violations, bad);
 }
 
 __global__ __launch_bounds__(256) void k_touchup_full(const Group* groups, RoundCtl* ctl)
@@ -107,7 +148,7 @@ __global__ __launch_bounds__(256) void k_touchup_full(const Group* groups, Round
 }
 
 hipError_t launch_touchup(GroupLists groups, const uint32_t* ngroups, const Fill* d_fills, uint32_t nfill, int full,
-                          RoundCtl* d_ctl, hipStream_t st)
+                          RoundCtl* d_ctl, bool graph, hipStream_t st)
 {
     RangeLists R;
     uint64_t items = nfill;
@@ -118,9 +159,12 @@ hipError_t launch_touchup(GroupLists groups, const uint32_t* ngroups, const Fill
     }
     R.fills = d_fills;
     R.nfill = nfill;
-    if (items)
-        k_touchup<<<(uint32_t)((items + 255) / 256), 256, 0, st>>>(R, d_ctl);
-    if (full)
+    uint64_t grid = (items + 255) / 256;
+    if (graph)
+        grid = std::min<uint64_t>(grid, kPersistTouch);
+    if (grid)
+        k_touchup<<<(uint32_t)grid, 256, 0, st>>>(R, d_ctl, graph);
+    if (full && !graph)
         for (uint32_t c = 0; c < kGroupClasses; ++c)
             if (ngroups[c])
                 k_touchup_full<<<ngroups[c], 256, 0, st>>>(groups.g[c], d_ctl);

@@ -101,6 +101,20 @@ struct LayoutParams {
     uint64_t cap;
     uint64_t seed;
     uint64_t model_base;  // local models start after the arrays' global models
+    // Capacities (entries) of the buffers a round writes: the lists classify
+    // appends to, and the next round's tables.  A round that would exceed
+    // one raises RoundCtl::overflow and ends the sort; the host sizes the
+    // buffers from bounds, so this only guards memory.
+    uint64_t cap_tasks, cap_fills, cap_groups[kGroupClasses];
+    uint64_t cap_keys, cap_chunks, cap_buckets, cap_entries, cap_samples, cap_blocks, cap_leafs, cap_models;
+};
+
+// Sizes of the running round, copied from the control block when the round
+// starts.  In graph mode the kernels are launched with upper-bound grids and
+// read their real sizes here (blocks beyond them exit at once).
+struct LiveCounts {
+    uint64_t chunk, nkeys, entries, samples, max_sample, buckets;
+    uint32_t ntasks, chunks, njobs, blocks, max_fanout, max_leaves;
 };
 
 // Counters the classify and layout kernels fill in; read by the host after
@@ -116,6 +130,7 @@ struct RoundCtl {
     uint64_t stall_keys;              // keys of tasks that made no progress (not scattered)
     uint32_t fallbacks;
     uint32_t violations;              // out-of-order seams found by the touch-up
+    uint32_t overflow;                // a list or table would have exceeded its buffer
     // written by the layout kernel for the next round
     uint64_t chunk;                   // keys per chunk
     uint64_t nkeys;                   // keys in the round's tasks
@@ -126,6 +141,11 @@ struct RoundCtl {
     uint32_t chunks, njobs, blocks;
     uint32_t max_fanout, max_leaves, max_level;
     uint32_t classified;              // classify workgroups finished (reset every round)
+    // written by the layout kernel, cumulative over the sort
+    uint32_t rounds;                  // rounds laid out with at least one task
+    uint32_t deepest;                 // largest task level laid out
+    uint64_t tasks_total;             // tasks over all rounds
+    LiveCounts cur;                   // graph mode: the running round's sizes
 };
 
 // Device model layout (doubles): header [xmin, xmax, rs, m'], then for the
@@ -179,14 +199,22 @@ __host__ __device__ inline uint32_t child_fanout(uint64_t n, uint32_t thresh, ui
 // kSampleBlock in LDS, then merge passes between d_sample and d_tmp), find
 // each leaf's most repeated value and fit.  d_best / d_first: per-leaf tables
 // that start and end at zero.
-hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t max_sample,
-                        uint64_t* d_sample, uint64_t* d_tmp, uint64_t* d_best, uint64_t* d_first,
-                        double* d_models, hipStream_t st);
-hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, hipStream_t st);
+// total: sample words of all jobs.  live (graph mode, may be null): njobs,
+// total_blocks and total are upper bounds and the real counts are read from
+// live (njobs, blocks, samples); max_sample, a bound on one job's sample,
+// fixes the merge passes (extra passes copy whole runs).
+hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t total,
+                        uint64_t max_sample, uint64_t* d_sample, uint64_t* d_tmp, uint64_t* d_best,
+                        uint64_t* d_first, double* d_models, const LiveCounts* live, hipStream_t st);
+// snapshot (graph mode): copy the next-round sizes into ctl->cur first and
+// clear ctl->buckets entries (nbuckets is then the grid's upper bound).
+hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, bool snapshot, hipStream_t st);
 hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                        const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint16_t* d_ids,
-                       uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, hipStream_t st);
-hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, hipStream_t st);
+                       uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, const LiveCounts* live,
+                       hipStream_t st);
+hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, const LiveCounts* live,
+                       hipStream_t st);
 size_t scan_tmp_entries(uint64_t n);
 // Classify every bucket of the round's tasks; the last workgroup to finish
 // then lays out the next round (see launch_layout) and copies the control
@@ -195,7 +223,8 @@ hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t*
                            const uint64_t* d_bstat, uint32_t thresh, uint32_t param_fanout,
                            Task* d_next, GroupLists groups, Fill* d_fills, uint8_t* d_skip,
                            uint32_t* d_task_flags, RoundCtl* d_ctl, uint32_t max_fanout,
-                           ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* host_ctl, hipStream_t st);
+                           ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* host_ctl, const LiveCounts* live,
+                           hipStream_t st);
 // Lay out the ctl->ntasks tasks of d_next: chunk size and offsets, and a
 // training job for each task that needs a local model; totals go to ctl and
 // to host_ctl.
@@ -205,10 +234,16 @@ hipError_t launch_layout(Task* d_next, ModelJob* d_jobs, const LayoutParams& lp,
 // (indexed by the task's cnt_base + position in the task).
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                           const uint16_t* d_ids, const uint64_t* d_pos, const uint8_t* d_skip,
-                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, hipStream_t st);
-hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, hipStream_t st);
-hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, hipStream_t st);
+                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, const LiveCounts* live,
+                          hipStream_t st);
+// Finishing kernels.  gctl (graph mode, may be null): ngroups / nfill are
+// upper bounds, the real counts are read from gctl, and nothing is done
+// while gctl->ntasks says partition rounds are still pending or after an
+// overflow.
+// In graph mode the grids are capped and the workgroups stride over the lists.
+hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, const RoundCtl* gctl, hipStream_t st);
+hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, const RoundCtl* gctl, hipStream_t st);
 hipError_t launch_touchup(GroupLists groups, const uint32_t* ngroups, const Fill* d_fills, uint32_t nfill,
-                          int full, RoundCtl* d_ctl, hipStream_t st);
+                          int full, RoundCtl* d_ctl, bool graph, hipStream_t st);
 
 }  // namespace lsort

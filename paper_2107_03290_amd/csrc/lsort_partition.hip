@@ -16,10 +16,33 @@ __device__ __forceinline__ uint32_t find_task(const Task* tasks, uint32_t ntasks
     return lo;
 }
 
-__global__ void k_round_init(uint64_t* bstat, uint64_t nbuckets, RoundCtl* ctl)
+__global__ void k_round_init(uint64_t* bstat, uint64_t nbuckets, RoundCtl* ctl, bool snapshot)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // ctl->buckets is not written by this kernel.  Its count is the last
+    // layout's, which never exceeds the buffer (zero after an overflow);
+    // when the round has no task it is stale and only clears more.
+    if (snapshot)
+        nbuckets = ctl->buckets;
     if (i == 0) {
+        if (snapshot) {
+            // a round without tasks runs nothing: its stale layout fields are ignored
+            const bool any = ctl->ntasks != 0;
+            LiveCounts c;
+            c.chunk = ctl->chunk;
+            c.nkeys = any ? ctl->nkeys : 0;
+            c.entries = any ? ctl->entries : 0;
+            c.samples = any ? ctl->samples : 0;
+            c.max_sample = any ? ctl->max_sample : 0;
+            c.buckets = any ? ctl->buckets : 0;
+            c.ntasks = ctl->ntasks;
+            c.chunks = any ? ctl->chunks : 0;
+            c.njobs = any ? ctl->njobs : 0;
+            c.blocks = any ? ctl->blocks : 0;
+            c.max_fanout = ctl->max_fanout;
+            c.max_leaves = ctl->max_leaves;
+            ctl->cur = c;
+        }
         ctl->ntasks = 0;
         ctl->classified = 0;
     }
@@ -29,9 +52,9 @@ __global__ void k_round_init(uint64_t* bstat, uint64_t nbuckets, RoundCtl* ctl)
     }
 }
 
-hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, hipStream_t st)
+hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, bool snapshot, hipStream_t st)
 {
-    k_round_init<<<(uint32_t)((nbuckets + 255) / 256 + 1), 256, 0, st>>>(d_bstat, nbuckets, d_ctl);
+    k_round_init<<<(uint32_t)((nbuckets + 255) / 256 + 1), 256, 0, st>>>(d_bstat, nbuckets, d_ctl, snapshot);
     return hipGetLastError();
 }
 
@@ -131,8 +154,14 @@ __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, const 
 
 __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32_t ntasks, uint64_t chunk,
                                                        const double* models, uint32_t* cnt, uint64_t* bstat,
-                                                       uint16_t* ids, uint32_t flags)
+                                                       uint16_t* ids, uint32_t flags, const LiveCounts* live)
 {
+    if (live) {
+        if (blockIdx.x >= live->chunks)
+            return;
+        ntasks = live->ntasks;
+        chunk = live->chunk;
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_task;
     if (threadIdx.x == 0)
@@ -178,11 +207,14 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32
 
 hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                        const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint16_t* d_ids,
-                       uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, hipStream_t st)
+                       uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, const LiveCounts* live,
+                       hipStream_t st)
 {
+    if (!total_chunks)
+        return hipSuccess;
     size_t smem = (((size_t)max_fanout * 20 + 15) & ~(size_t)15) + model_lds_bytes(max_leaves);
     k_hist<<<total_chunks, kHistThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_cnt, d_bstat, d_ids,
-                                                     flags);
+                                                     flags, live);
     return hipGetLastError();
 }
 
@@ -215,7 +247,8 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
     __shared__ uint64_t wsum[kLayoutQ][16];
     __shared__ uint64_t carry[kLayoutQ];
     const uint32_t NT = blockDim.x;
-    const uint32_t nt = ctl->ntasks;
+    // after an overflow the lists are incomplete: lay out nothing
+    const uint32_t nt = ctl->overflow ? 0u : ctl->ntasks;
     if (threadIdx.x == 0) {
         s_keys = 0;
         s_maxm = 0;
@@ -338,8 +371,19 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
     atomicMax(&s_maxl, my_maxl);
     __syncthreads();
     if (threadIdx.x == 0) {
+        const bool over = ctl->overflow || nkeys > lp.cap_keys || carry[0] > lp.cap_chunks ||
+                          carry[1] > lp.cap_buckets || carry[2] > lp.cap_entries || carry[4] > lp.cap_tasks ||
+                          carry[5] > lp.cap_samples || carry[6] > lp.cap_leafs || carry[7] > lp.cap_models ||
+                          carry[8] > lp.cap_blocks;
+        if (over) {
+            // no next round: every size it would be launched with is zero
+            ctl->overflow = 1;
+            ctl->ntasks = 0;
+            for (uint32_t j = 0; j < kLayoutQ; ++j)
+                carry[j] = 0;
+        }
         ctl->chunk = chunk;
-        ctl->nkeys = nkeys;
+        ctl->nkeys = over ? 0 : nkeys;
         ctl->chunks = (uint32_t)carry[0];
         ctl->buckets = carry[1];
         ctl->entries = carry[2];
@@ -352,6 +396,11 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
         ctl->max_leaves = s_maxl;
         ctl->max_level = s_maxlev;
         ctl->max_sample = s_maxm;
+        if (nt && !over) {
+            ctl->rounds += 1;
+            ctl->tasks_total += nt;
+        }
+        ctl->deepest = max(ctl->deepest, s_maxlev);
         __threadfence();
         *host_ctl = *ctl;      // publish to the host without a copy
         __threadfence_system();
@@ -375,8 +424,14 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
                                                   uint32_t thresh, uint32_t param_fanout, Task* next,
                                                   GroupLists groups, Fill* fills, uint8_t* skip,
                                                   uint32_t* task_flags, RoundCtl* ctl, ModelJob* jobs,
-                                                  LayoutParams lp, RoundCtl* host_ctl)
+                                                  LayoutParams lp, RoundCtl* host_ctl, const LiveCounts* live)
 {
+    uint32_t ntasks = gridDim.x;
+    if (live) {
+        ntasks = live->ntasks;
+        if (blockIdx.x >= ntasks)
+            return;
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     const Task T = tasks[blockIdx.x];
     const uint32_t f = T.fanout;
@@ -392,7 +447,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
     uint8_t* kind = reinterpret_cast<uint8_t*>(fidx + f);
     __shared__ uint32_t ws_u[17];
     __shared__ int32_t ws_i[17];
-    __shared__ uint32_t s_gb[kGroupClasses], s_tb, s_fb, s_noprog, s_nfb;
+    __shared__ uint32_t s_gb[kGroupClasses], s_tb, s_fb, s_noprog, s_nfb, s_over;
     __shared__ unsigned long long s_fkeys, s_gkeys;
     if (threadIdx.x == 0) {
         s_noprog = 0;
@@ -494,13 +549,20 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
             atomicAdd((unsigned long long*)&ctl->group_keys, s_gkeys);
         if (s_noprog)
             atomicAdd((unsigned long long*)&ctl->stall_keys, (unsigned long long)T.n);
+        bool over = (uint64_t)s_tb + nt > lp.cap_tasks || (uint64_t)s_fb + nf > lp.cap_fills;
+        for (uint32_t c = 0; c < kGroupClasses; ++c)
+            over = over || (uint64_t)s_gb[c] + ng[c] > lp.cap_groups[c];
+        if (over)
+            atomicOr(&ctl->overflow, 1u);
+        s_over = over;
         task_flags[blockIdx.x] = s_noprog ? kNoScatter : 0u;
     }
     __syncthreads();
     const bool noprog = s_noprog != 0;
+    const bool over = s_over != 0;
     // where the keys of this round's buckets live after the scatter
     const uint64_t* moved = (noprog ? (T.src ? T.scratch : T.keys) : (T.src ? T.keys : T.scratch)) + T.start;
-    for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
+    for (uint32_t b = over ? f : threadIdx.x; b < f; b += blockDim.x) {
         const uint8_t kl = kind[b];
         const uint8_t k = kl & ~kLead;
         const uint64_t sz = bst[b + 1] - bst[b];
@@ -571,7 +633,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0)
-        s_last = atomicAdd(&ctl->classified, 1u) == gridDim.x - 1;
+        s_last = atomicAdd(&ctl->classified, 1u) == ntasks - 1;
     __syncthreads();
     if (s_last) {
         __threadfence();
@@ -582,13 +644,16 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
 hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t* d_pos, const uint64_t* d_bstat,
                            uint32_t thresh, uint32_t param_fanout, Task* d_next, GroupLists groups, Fill* d_fills,
                            uint8_t* d_skip, uint32_t* d_task_flags, RoundCtl* d_ctl, uint32_t max_fanout,
-                           ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* host_ctl, hipStream_t st)
+                           ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* host_ctl, const LiveCounts* live,
+                           hipStream_t st)
 {
+    if (!ntasks)
+        return hipSuccess;
     size_t smem = (size_t)(max_fanout + 1) * 8 + (size_t)max_fanout * (4 + 4 + 4 + 4 + 4 + 4 + 1) + 64;
     // a round with a few wide tasks (level 0) gets wide workgroups
     const uint32_t threads = (ntasks <= 64 && max_fanout >= 1024) ? 1024u : 256u;
     k_classify<<<ntasks, threads, smem, st>>>(d_tasks, d_pos, d_bstat, thresh, param_fanout, d_next, groups,
-                                          d_fills, d_skip, d_task_flags, d_ctl, d_jobs, lp, host_ctl);
+                                          d_fills, d_skip, d_task_flags, d_ctl, d_jobs, lp, host_ctl, live);
     return hipGetLastError();
 }
 
@@ -678,8 +743,15 @@ __device__ __forceinline__ void scatter_body(const Task& T, const uint64_t* src,
 template <uint32_t KPT>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, uint32_t ntasks, uint64_t chunk,
                                                              const uint16_t* ids, const uint64_t* pos,
-                                                             const uint8_t* skip, const uint32_t* task_flags)
+                                                             const uint8_t* skip, const uint32_t* task_flags,
+                                                             const LiveCounts* live)
 {
+    if (live) {
+        if (blockIdx.x >= live->chunks)
+            return;
+        ntasks = live->ntasks;
+        chunk = live->chunk;
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr uint32_t TILE = KPT * kScatterThreads;
     __shared__ uint32_t s_task;
@@ -710,21 +782,24 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, 
 
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                           const uint16_t* d_ids, const uint64_t* d_pos, const uint8_t* d_skip,
-                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, hipStream_t st)
+                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, const LiveCounts* live,
+                          hipStream_t st)
 {
+    if (!total_chunks)
+        return hipSuccess;
     const size_t smem = scatter_lds_bytes(tile, max_fanout);
     switch (tile) {
     case 1024:
         k_scatter<1><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
-                                                                  d_task_flags);
+                                                                  d_task_flags, live);
         break;
     case 2048:
         k_scatter<2><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
-                                                                  d_task_flags);
+                                                                  d_task_flags, live);
         break;
     case 4096:
         k_scatter<4><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
-                                                                  d_task_flags);
+                                                                  d_task_flags, live);
         break;
     default:
         return hipErrorInvalidValue;

@@ -9,8 +9,14 @@ namespace lsort {
 constexpr uint32_t kScanBlock = 4096;
 constexpr uint32_t kScanThreads = 256;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* in, uint64_t n, uint64_t* sums)
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* in, uint64_t n, uint64_t* sums,
+                                                              const LiveCounts* live)
 {
+    if (live) {
+        n = live->entries;
+        if ((uint64_t)blockIdx.x * kScanBlock >= n)
+            return;
+    }
     __shared__ uint64_t ws[kScanThreads / 64];
     const uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
     uint64_t s = 0;
@@ -29,8 +35,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* in
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, uint64_t n, const uint64_t* sums,
-                                                            uint64_t* out)
+                                                            uint64_t* out, const LiveCounts* live)
 {
+    if (live) {
+        n = live->entries;
+        if ((uint64_t)blockIdx.x * kScanBlock >= n)
+            return;
+    }
     __shared__ uint64_t ws[kScanThreads / 64 + 1];
     __shared__ uint64_t s_base;
     // prefix of this block: the sums of every earlier block
@@ -86,13 +97,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, 
 
 size_t scan_tmp_entries(uint64_t n) { return (size_t)((n + kScanBlock - 1) / kScanBlock) + 1; }
 
-hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, hipStream_t st)
+hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, const LiveCounts* live,
+                       hipStream_t st)
 {
     const uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
     if (!nb)
         return hipSuccess;
-    k_scan_reduce<<<nb, kScanThreads, 0, st>>>(d_in, n, d_tmp);
-    k_scan_down<<<nb, kScanThreads, 0, st>>>(d_in, n, d_tmp, d_out);
+    k_scan_reduce<<<nb, kScanThreads, 0, st>>>(d_in, n, d_tmp, live);
+    k_scan_down<<<nb, kScanThreads, 0, st>>>(d_in, n, d_tmp, d_out, live);
     return hipGetLastError();
 }
 

@@ -47,7 +47,6 @@ struct ls_server {
     int device = 0;
     uint64_t budget = 0;
     ls_params params{};
-    bool has_params = false;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request> queue;
@@ -108,7 +107,7 @@ void worker_main(ls_server* S)
             for (auto& r : batch)
                 arrays.push_back(ls_array{r.keys, r.n, (uint32_t)r.dtype, 0});
             status = ls_sort_arrays(ctx, arrays.data(), arrays.size(), (ls_stream_t)st,
-                                    S->has_params ? &S->params : nullptr);
+                                    &S->params);
             if (status == LS_OK && hipStreamSynchronize(st) != hipSuccess)
                 status = LS_ERR_HIP;
             if (status != LS_OK && batch.size() > 1) {
@@ -116,7 +115,7 @@ void worker_main(ls_server* S)
                 for (auto& r : batch) {
                     ls_array one{r.keys, r.n, (uint32_t)r.dtype, 0};
                     ls_status s1 = ls_sort_arrays(ctx, &one, 1, (ls_stream_t)st,
-                                                  S->has_params ? &S->params : nullptr);
+                                                  &S->params);
                     if (s1 == LS_OK)
                         s1 = hipStreamSynchronize(st) == hipSuccess ? LS_OK : LS_ERR_HIP;
                     r.n = (uint64_t)s1;     // reuse the field to carry the status below
@@ -166,7 +165,10 @@ ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
     S->budget = hbm_budget_bytes;
     if (p) {
         S->params = *p;
-        S->has_params = true;
+    } else {
+        // batches small enough run as graph replays by default
+        ls_default_params(&S->params);
+        S->params.flags |= LS_FLAG_GRAPH;
     }
     for (uint32_t i = 0; i < max_inflight; ++i)
         S->workers.emplace_back(worker_main, S);

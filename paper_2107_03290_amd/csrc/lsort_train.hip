@@ -100,8 +100,14 @@ __device__ __forceinline__ uint32_t root_leaf(double x, const Root& R, uint32_t 
 }
 
 // Gather the sample (order-preserving words), 16 independent loads per lane.
-__global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint32_t njobs, uint64_t* sample)
+__global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint32_t njobs, uint64_t* sample,
+                                                      const LiveCounts* live)
 {
+    if (live) {
+        if (blockIdx.x >= live->blocks)
+            return;
+        njobs = live->njobs;
+    }
     __shared__ uint32_t s_job;
     if (threadIdx.x == 0)
         s_job = find_job(jobs, njobs, blockIdx.x);
@@ -124,8 +130,14 @@ __global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint
 }
 
 // Sort the block's run of up to kSampleBlock sample words in LDS.
-__global__ __launch_bounds__(256) void k_train_sort_runs(const ModelJob* jobs, uint32_t njobs, uint64_t* sample)
+__global__ __launch_bounds__(256) void k_train_sort_runs(const ModelJob* jobs, uint32_t njobs, uint64_t* sample,
+                                                         const LiveCounts* live)
 {
+    if (live) {
+        if (blockIdx.x >= live->blocks)
+            return;
+        njobs = live->njobs;
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t* s = reinterpret_cast<uint64_t*>(smem);
     __shared__ uint32_t s_job;
@@ -153,8 +165,12 @@ __global__ __launch_bounds__(256) void k_train_sort_runs(const ModelJob* jobs, u
 // left run lands after the right run's smaller words, a word of the right run
 // after the left run's words not above it, so equal words keep their order.
 __global__ __launch_bounds__(256) void k_train_merge(const ModelJob* jobs, uint32_t njobs, const uint64_t* src,
-                                                     uint64_t* dst, uint64_t w, uint64_t total)
+                                                     uint64_t* dst, uint64_t w, uint64_t total, const LiveCounts* live)
 {
+    if (live) {
+        njobs = live->njobs;
+        total = live->samples;
+    }
     const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= total)
         return;
@@ -191,8 +207,13 @@ __global__ __launch_bounds__(256) void k_train_merge(const ModelJob* jobs, uint3
 // and each lane walks 16 consecutive ones; only a run that reaches past the
 // lane's range is searched for in global memory.
 __global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint32_t njobs, const uint64_t* sorted,
-                                                     uint64_t* best, uint64_t* firstc)
+                                                     uint64_t* best, uint64_t* firstc, const LiveCounts* live)
 {
+    if (live) {
+        if (blockIdx.x >= live->blocks)
+            return;
+        njobs = live->njobs;
+    }
     constexpr uint32_t kPer = kSampleBlock / 256;
     __shared__ uint32_t s_job;
     __shared__ unsigned long long s_best[kMaxLeaves], s_first[kMaxLeaves];
@@ -256,8 +277,10 @@ __global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint3
 
 // Knots and segments of one job's model (one block per job).
 __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const uint64_t* sorted, uint64_t* best,
-                                                   uint64_t* firstc, double* models)
+                                                   uint64_t* firstc, double* models, const LiveCounts* live)
 {
+    if (live && blockIdx.x >= live->njobs)
+        return;
     __shared__ int32_t prv[kMaxLeaves];
     __shared__ int32_t nxt[kMaxLeaves];      // reversed index
     __shared__ uint32_t kB[kMaxLeaves], kd[kMaxLeaves];   // knot: sample values below it, its copies
@@ -380,26 +403,24 @@ __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const u
     }
 }
 
-hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t max_sample,
-                        uint64_t* d_sample, uint64_t* d_tmp, uint64_t* d_best, uint64_t* d_first,
-                        double* d_models, hipStream_t st)
+hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t total,
+                        uint64_t max_sample, uint64_t* d_sample, uint64_t* d_tmp, uint64_t* d_best,
+                        uint64_t* d_first, double* d_models, const LiveCounts* live, hipStream_t st)
 {
-    if (!njobs)
+    if (!njobs || !total_blocks || !total)
         return hipSuccess;
-    // every job's sample lies inside its blocks: sample_off + m <= block0 * kSampleBlock + ...
-    const uint64_t total = (uint64_t)total_blocks * kSampleBlock;
-    k_train_sample<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, d_sample);
-    k_train_sort_runs<<<total_blocks, 256, (size_t)base_pad(kSampleBlock) * 8, st>>>(d_jobs, njobs, d_sample);
+    k_train_sample<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, d_sample, live);
+    k_train_sort_runs<<<total_blocks, 256, (size_t)base_pad(kSampleBlock) * 8, st>>>(d_jobs, njobs, d_sample, live);
     uint64_t* src = d_sample;
     uint64_t* dst = d_tmp;
     for (uint64_t w = kSampleBlock; w < max_sample; w *= 2) {
-        k_train_merge<<<(uint32_t)((total + 255) / 256), 256, 0, st>>>(d_jobs, njobs, src, dst, w, total);
+        k_train_merge<<<(uint32_t)((total + 255) / 256), 256, 0, st>>>(d_jobs, njobs, src, dst, w, total, live);
         uint64_t* t = src;
         src = dst;
         dst = t;
     }
-    k_train_modes<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, src, d_best, d_first);
-    k_train_fit<<<njobs, 256, 0, st>>>(d_jobs, src, d_best, d_first, d_models);
+    k_train_modes<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, src, d_best, d_first, live);
+    k_train_fit<<<njobs, 256, 0, st>>>(d_jobs, src, d_best, d_first, d_models, live);
     return hipGetLastError();
 }
 
