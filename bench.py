@@ -196,6 +196,9 @@ def bench_served(args, torch, ls):
     total = int(sum(a.size for a in reqs))
     print("served: %d requests, %d keys generated in %.1f s" % (R, total, time.perf_counter() - t0),
           file=sys.stderr, flush=True)
+    # graph mode (LS_FLAG_GRAPH): requests and batches of up to 2^22 keys run
+    # as replays of captured graphs, on the plain path and in the server
+    gp = ls.params(flags=ls.FLAG_GRAPH) if args.graph == "on" else ls.params()
     pristine = [to_device(a, torch) for a in reqs]
     work = [torch.empty_like(t) for t in pristine]
     ref = [torch.empty_like(t) for t in pristine]
@@ -209,7 +212,7 @@ def bench_served(args, torch, ls):
     # warm-up both paths (buffers grow once)
     restore(ref)
     for t in ref[:8]:
-        S.sort_(t)
+        S.sort_(t, gp)
     torch.cuda.synchronize()
 
     def run_plain(arrival):
@@ -220,14 +223,14 @@ def bench_served(args, torch, ls):
             now = time.perf_counter() - start
             if now < a:
                 time.sleep(a - now)
-            S.sort_(t)
+            S.sort_(t, gp)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - start - a)
         return time.perf_counter() - start, lat
 
     def run_served(arrival):
         restore(work)
-        srv = ls.Server(0, hbm_budget=args.budget_gb << 30, max_inflight=args.inflight)
+        srv = ls.Server(0, hbm_budget=args.budget_gb << 30, max_inflight=args.inflight, p=gp)
         tickets = [None] * R
         sub_t = [0.0] * R
         start = time.perf_counter()
@@ -273,7 +276,7 @@ def bench_served(args, torch, ls):
         "ms_per_step": ws * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+u64", "data": "synthetic (seeded generator; no dataset)",
         "config": {"workload": "served_%d_requests" % R, "keys": total, "budget_gb": args.budget_gb,
-                   "max_inflight": args.inflight},
+                   "max_inflight": args.inflight, "graph": args.graph == "on"},
         "burst": {"served_keys_per_s": total / ws, "plain_keys_per_s": total / wp,
                   "served_p50_s": pct(lsv, 50), "served_p99_s": pct(lsv, 99),
                   "plain_p50_s": pct(lp, 50), "plain_p99_s": pct(lp, 99), "batches": st_b["batches"],
@@ -405,6 +408,8 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="requests of the served workload")
     ap.add_argument("--budget-gb", type=int, default=200)
     ap.add_argument("--inflight", type=int, default=2)
+    ap.add_argument("--graph", choices=("on", "off"), default="on",
+                    help="served workload: run requests and batches of up to 2^22 keys as graph replays")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_profiles(args)

@@ -219,6 +219,10 @@ ls_status ls_server_wait(ls_server* s, uint64_t ticket, int timeout_ms, double* 
  * admitted bytes, [4] currently admitted bytes, [5] queued requests. */
 ls_status ls_server_stats(ls_server* s, uint64_t* out6);
 
+/* Copy the message of the latest failed batch (empty if none) into buf
+ * (cap bytes, NUL-terminated, truncated to fit). */
+ls_status ls_server_last_error(ls_server* s, char* buf, size_t cap);
+
 /* Drain every request and stop. */
 ls_status ls_server_destroy(ls_server* s);
 

@@ -44,7 +44,7 @@ EXPORTS = (
     "ls_last_stats", "ls_last_profile", "ls_profile_reset", "ls_status_string", "ls_last_error",
     "ls_model_train", "ls_stage_hist",
     "ls_server_create", "ls_server_submit", "ls_server_wait", "ls_server_stats",
-    "ls_server_destroy",
+    "ls_server_last_error", "ls_server_destroy",
 )
 
 
@@ -120,6 +120,7 @@ def lib() -> ctypes.CDLL:
             L.ls_server_submit.argtypes = [vp, ctypes.c_int, vp, sz, P(u64)]
             L.ls_server_wait.argtypes = [vp, u64, ctypes.c_int, P(ctypes.c_double)]
             L.ls_server_stats.argtypes = [vp, P(u64)]
+            L.ls_server_last_error.argtypes = [vp, ctypes.c_char_p, sz]
             L.ls_server_destroy.argtypes = [vp]
             _lib = L
         return _lib
@@ -396,7 +397,9 @@ class Server:
         lat = ctypes.c_double()
         st = lib().ls_server_wait(self._s, ticket, timeout_ms, ctypes.byref(lat))
         if st != 0:
-            raise LsortError(st, "wait")
+            buf = ctypes.create_string_buffer(512)
+            lib().ls_server_last_error(self._s, buf, 512)
+            raise LsortError(st, "wait: " + buf.value.decode(errors="replace"))
         return lat.value
 
     def stats(self) -> dict:

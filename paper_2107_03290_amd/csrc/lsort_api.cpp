@@ -13,8 +13,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -37,6 +39,7 @@ struct DevBuf {
 
 struct PinBuf {
     void* p = nullptr;
+    void* dev = nullptr;   // its device address (mapped)
     size_t cap = 0;
 };
 
@@ -67,8 +70,17 @@ uint64_t sample_size(uint64_t n, double rate, uint64_t cap)
 struct GraphEntry {
     uint64_t keys, arrays, gen;
     Params P;
+    uint32_t rounds;      // partition rounds in the replay
     hipGraphExec_t exec;
-    void* list0;          // the task list the replay uploads round 0 into and ends with
+    void* list_final;     // the task list the replay's last layout writes
+};
+
+// Partition rounds the last batch of a size class needed (the next replay
+// of the class holds that many).
+struct RoundsHint {
+    uint64_t keys, arrays;
+    Params P;
+    uint32_t rounds;
 };
 
 uint32_t group_class(uint32_t n)
@@ -81,14 +93,14 @@ uint32_t group_class(uint32_t n)
 struct ls_ctx {
     int device = 0;
     std::string err;
-    DevBuf scratch, tune, ids, models, sample, sample2, tbest, tfirst, gjobs, ljobs, tasks, next, cnt, pos, scantmp,
+    DevBuf scratch, tune, ids, models, sample, sample2, tbest, tfirst, tnf, gjobs, ljobs, tasks, next, cnt, pos, scantmp,
         bstat,
         skip, tflags, fills, ctl;
     DevBuf groups[kGroupClasses];
-    PinBuf pin_tasks, pin_jobs, pin_groups[kGroupClasses];
+    PinBuf pin_jobs;
+    PinBuf estage;                   // round-0 lists of a host-driven sort (read by the upload kernel)
     RoundCtl* h_ctl = nullptr;       // pinned, device-mapped: kernels publish the control block here
     RoundCtl* d_h_ctl = nullptr;     // its device address
-    RoundCtl* h_ctl_init = nullptr;  // pinned upload
     uint64_t stats[8] = {0};
     uint32_t dev_status = 0;
     size_t lds_limit = 65536;
@@ -100,10 +112,85 @@ struct ls_ctx {
     uint64_t gen = 0;                    // bumped whenever a buffer is reallocated
     PinBuf gstage;                       // staging of the replays' uploads
     hipStream_t cap_stream = nullptr;    // capture only; replays run on the caller's stream
+    // finish: the base-case size classes run side by side
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     std::vector<GraphEntry> graphs;
+    std::vector<RoundsHint> hints;
 };
 
 namespace {
+
+// Graph captures are kept apart from every other HIP call the library makes
+// in the process (other contexts, other threads): a capture waits until no
+// library call is in progress, and library calls wait while a capture is in
+// progress or waiting.  A thread that captures inside a library call steps
+// out of it for the capture.
+struct CaptureGate {
+    std::mutex m;
+    std::condition_variable cv;
+    int active = 0, waiting = 0;
+    bool capturing = false;
+};
+
+CaptureGate& capture_gate()
+{
+    static CaptureGate g;
+    return g;
+}
+
+thread_local int t_gate_depth = 0;
+
+struct GateUse {
+    GateUse()
+    {
+        if (t_gate_depth++ != 0)
+            return;
+        CaptureGate& G = capture_gate();
+        std::unique_lock<std::mutex> lk(G.m);
+        G.cv.wait(lk, [&] { return !G.capturing && G.waiting == 0; });
+        ++G.active;
+    }
+    ~GateUse()
+    {
+        if (--t_gate_depth != 0)
+            return;
+        CaptureGate& G = capture_gate();
+        {
+            std::lock_guard<std::mutex> lk(G.m);
+            --G.active;
+        }
+        G.cv.notify_all();
+    }
+};
+
+struct GateCapture {
+    bool inside;
+    GateCapture()
+    {
+        CaptureGate& G = capture_gate();
+        std::unique_lock<std::mutex> lk(G.m);
+        inside = t_gate_depth > 0;
+        if (inside)
+            --G.active;
+        ++G.waiting;
+        G.cv.notify_all();
+        G.cv.wait(lk, [&] { return !G.capturing && G.active == 0; });
+        --G.waiting;
+        G.capturing = true;
+    }
+    ~GateCapture()
+    {
+        CaptureGate& G = capture_gate();
+        std::unique_lock<std::mutex> lk(G.m);
+        G.capturing = false;
+        G.cv.notify_all();
+        if (inside) {
+            G.cv.wait(lk, [&] { return !G.capturing && G.waiting == 0; });
+            ++G.active;
+        }
+    }
+};
 
 ls_status fail(ls_ctx* C, ls_status s, const std::string& msg)
 {
@@ -157,10 +244,14 @@ ls_status ensure_pinned(ls_ctx* C, PinBuf& b, size_t bytes, hipStream_t st)
     HIPCHECK(C, hipStreamSynchronize(st));
     if (b.p)
         HIPCHECK(C, hipHostFree(b.p));
-    b.p = nullptr;
+    b.p = b.dev = nullptr;
     size_t nb = std::max<size_t>({bytes, b.cap * 2, 4096});
-    if (hipHostMalloc(&b.p, nb, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&b.p, nb, hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer(&b.dev, b.p, 0) != hipSuccess) {
         (void)hipGetLastError();
+        if (b.p)
+            (void)hipHostFree(b.p);
+        b.p = b.dev = nullptr;
         b.cap = 0;
         return fail(C, LS_ERR_NOMEM, "pinned host allocation failed");
     }
@@ -311,11 +402,11 @@ ls_status train(ls_ctx* C, const DevBuf& jobs, uint32_t njobs, uint32_t blocks, 
     TRY(ensure(C, C->models, (model_base + models) * sizeof(double), st, model_base * sizeof(double)));
     TRY(ensure(C, C->sample, samples * 8, st));
     TRY(ensure(C, C->sample2, samples * 8, st));
-    // the per-leaf tables start at zero and the fit kernel leaves them at
-    // zero; only freshly allocated memory needs clearing
-    DevBuf* tabs[2] = {&C->tbest, &C->tfirst};
-    const size_t need[2] = {leafs * 8, leafs * 8};
-    for (int i = 0; i < 2; ++i) {
+    // the per-leaf and per-job tables start at zero and the fit kernel
+    // leaves them at zero; only freshly allocated memory needs clearing
+    DevBuf* tabs[3] = {&C->tbest, &C->tfirst, &C->tnf};
+    const size_t need[3] = {leafs * 8, leafs * 8, (size_t)njobs * 16};
+    for (int i = 0; i < 3; ++i) {
         const void* before = tabs[i]->p;
         TRY(ensure(C, *tabs[i], need[i], st));
         if (tabs[i]->p != before)
@@ -325,7 +416,7 @@ ls_status train(ls_ctx* C, const DevBuf& jobs, uint32_t njobs, uint32_t blocks, 
         prof->begin(0);
     HIPCHECK(C, launch_train((const ModelJob*)jobs.p, njobs, blocks, samples, max_sample, (uint64_t*)C->sample.p,
                              (uint64_t*)C->sample2.p, (uint64_t*)C->tbest.p, (uint64_t*)C->tfirst.p,
-                             (double*)C->models.p, nullptr, st));
+                             (uint64_t*)C->tnf.p, (double*)C->models.p, nullptr, st));
     if (prof)
         prof->end((double)samples * 16.0);
     return LS_OK;
@@ -391,6 +482,67 @@ void prepare(std::vector<Array>& arrays, void* scratch, const Params& P, bool ms
         B.tasks.push_back(t);
     }
     B.total = off;
+}
+
+// Where the round-0 lists of a batch sit in a staging area (control block
+// first), for the given capacities.
+struct StageLayout {
+    size_t off_tasks, off_jobs, off_groups[kGroupClasses], bytes;
+};
+
+StageLayout stage_layout(uint64_t tasks, uint64_t jobs, const uint64_t* groups)
+{
+    StageLayout L;
+    size_t off = (sizeof(RoundCtl) + 255) & ~(size_t)255;
+    L.off_tasks = off;
+    off += tasks * sizeof(Task);
+    L.off_jobs = off;
+    off += jobs * sizeof(ModelJob);
+    for (uint32_t c = 0; c < kGroupClasses; ++c) {
+        L.off_groups[c] = off;
+        off += groups[c] * sizeof(Group);
+    }
+    L.bytes = off;
+    return L;
+}
+
+// Write a batch's round-0 lists and initial control block into a staging
+// area laid out by L.
+void fill_stage(unsigned char* sp, const StageLayout& L, const Batch& B)
+{
+    RoundCtl* c0 = reinterpret_cast<RoundCtl*>(sp);
+    std::memset(c0, 0, sizeof(RoundCtl));
+    c0->ntasks = (uint32_t)B.tasks.size();
+    for (uint32_t c = 0; c < kGroupClasses; ++c) {
+        c0->ngroups[c] = (uint32_t)B.groups0[c].size();
+        if (!B.groups0[c].empty())
+            std::memcpy(sp + L.off_groups[c], B.groups0[c].data(), B.groups0[c].size() * sizeof(Group));
+    }
+    // the global training reads its sizes here
+    c0->cur.njobs = (uint32_t)B.tr.jobs.size();
+    c0->cur.blocks = B.tr.blocks;
+    c0->cur.samples = B.tr.samples;
+    c0->cur.max_sample = B.tr.max_sample;
+    if (!B.tasks.empty())
+        std::memcpy(sp + L.off_tasks, B.tasks.data(), B.tasks.size() * sizeof(Task));
+    if (!B.tr.jobs.empty())
+        std::memcpy(sp + L.off_jobs, B.tr.jobs.data(), B.tr.jobs.size() * sizeof(ModelJob));
+}
+
+UploadPlan upload_plan(ls_ctx* C, const PinBuf& stage, const StageLayout& L)
+{
+    UploadPlan U;
+    U.stage = (const unsigned char*)stage.dev;
+    U.ctl = (RoundCtl*)C->ctl.p;
+    U.tasks = (Task*)C->next.p;
+    U.jobs = (ModelJob*)C->gjobs.p;
+    U.off_tasks = L.off_tasks;
+    U.off_jobs = L.off_jobs;
+    for (uint32_t c = 0; c < kGroupClasses; ++c) {
+        U.groups[c] = (Group*)C->groups[c].p;
+        U.off_groups[c] = L.off_groups[c];
+    }
+    return U;
 }
 
 constexpr uint64_t kUnbounded = ~0ull;
@@ -502,6 +654,39 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
     return LS_OK;
 }
 
+// The base case over the three size classes and the fills: classes 1 and
+// 2 on side streams forked from st and joined back, class 0 and the fills on
+// st (under capture, parallel branches of the graph).
+ls_status launch_finish_lists(ls_ctx* C, const GroupLists& gl, const uint32_t* ngroups, const Fill* fills,
+                              uint32_t nfill, const RoundCtl* gctl, hipStream_t st)
+{
+    const bool fork = gctl || (ngroups[1] && ngroups[2]) || ((ngroups[1] || ngroups[2]) && (ngroups[0] || nfill));
+    if (!fork) {
+        for (uint32_t c = 0; c < kGroupClasses; ++c)
+            HIPCHECK(C, launch_base(gl.g[c], ngroups[c], c, gctl, st));
+        HIPCHECK(C, launch_fill(fills, nfill, gctl, st));
+        return LS_OK;
+    }
+    if (!C->ev_fork) {
+        for (int i = 0; i < 2; ++i)
+            HIPCHECK(C, hipStreamCreateWithFlags(&C->side[i], hipStreamNonBlocking));
+        HIPCHECK(C, hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
+        for (int i = 0; i < 2; ++i)
+            HIPCHECK(C, hipEventCreateWithFlags(&C->ev_join[i], hipEventDisableTiming));
+    }
+    HIPCHECK(C, hipEventRecord(C->ev_fork, st));
+    for (uint32_t i = 0; i < 2; ++i) {
+        HIPCHECK(C, hipStreamWaitEvent(C->side[i], C->ev_fork, 0));
+        HIPCHECK(C, launch_base(gl.g[2 - i], ngroups[2 - i], 2 - i, gctl, C->side[i]));
+        HIPCHECK(C, hipEventRecord(C->ev_join[i], C->side[i]));
+    }
+    HIPCHECK(C, launch_base(gl.g[0], ngroups[0], 0, gctl, st));
+    HIPCHECK(C, launch_fill(fills, nfill, gctl, st));
+    for (int i = 0; i < 2; ++i)
+        HIPCHECK(C, hipStreamWaitEvent(st, C->ev_join[i], 0));
+    return LS_OK;
+}
+
 // Finish: LDS base case, all-equal fills, touch-up; reads the final control
 // block back.
 ls_status finish_eager(ls_ctx* C, hipStream_t st, const Params& P, Prof& prof, uint64_t group0_keys)
@@ -511,12 +696,18 @@ ls_status finish_eager(ls_ctx* C, hipStream_t st, const Params& P, Prof& prof, u
     for (uint32_t c = 0; c < kGroupClasses; ++c)
         gl.g[c] = (Group*)C->groups[c].p;
     const double gkeys = (double)F.group_keys + (double)group0_keys;
-    prof.begin(5);
-    HIPCHECK(C, launch_base(gl, F.ngroups, nullptr, st));
-    prof.end(16.0 * gkeys);
-    prof.begin(6);
-    HIPCHECK(C, launch_fill((const Fill*)C->fills.p, F.nfill, nullptr, st));
-    prof.end(8.0 * (double)F.fillkeys);
+    if (prof.on) {
+        // timed one kernel class at a time
+        prof.begin(5);
+        for (uint32_t c = 0; c < kGroupClasses; ++c)
+            HIPCHECK(C, launch_base(gl.g[c], F.ngroups[c], c, nullptr, st));
+        prof.end(16.0 * gkeys);
+        prof.begin(6);
+        HIPCHECK(C, launch_fill((const Fill*)C->fills.p, F.nfill, nullptr, st));
+        prof.end(8.0 * (double)F.fillkeys);
+    } else {
+        TRY(launch_finish_lists(C, gl, F.ngroups, (const Fill*)C->fills.p, F.nfill, nullptr, st));
+    }
     prof.begin(7);
     HIPCHECK(C, launch_touchup(gl, F.ngroups, (const Fill*)C->fills.p, F.nfill,
                                (P.flags & LS_FLAG_DEBUG_TOUCHUP) ? 1 : 0, (RoundCtl*)C->ctl.p, false, st));
@@ -565,19 +756,21 @@ ls_status conclude(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const 
 //
 // A batch of at most kGraphMaxKeys keys can run as one replay of a HIP graph
 // captured for its size class (keys and arrays rounded up to powers of two):
-// uploads of the round-0 lists, global training, layout, kGraphRounds
-// partition rounds and the finish.  Every buffer is sized from bounds on what
-// a round of the class can produce, the kernels are launched with grids for
-// those bounds and read their real sizes from the control block, and rounds
-// past the last task run nothing.  A batch that needs more rounds continues
-// on the host-driven path from the state the replay left.
+// uploads of the round-0 lists, global training, layout, R partition rounds
+// and the finish.  R is the number of rounds the class's last batch needed
+// (at most kGraphMaxRounds; one graph per R).  Every buffer is sized from
+// bounds on what kGraphMaxRounds rounds of the class can produce, the kernels
+// are launched with grids for those bounds and read their real sizes from
+// the control block, and rounds past the last task run nothing.  A batch
+// that needs more rounds continues on the host-driven path from the state
+// the replay left.
 
 constexpr uint64_t kGraphMinKeys = 1ull << 16;
 constexpr uint64_t kGraphMaxKeys = 1ull << 22;
 constexpr uint64_t kGraphMinArrays = 64;
 constexpr uint64_t kGraphMaxArrays = 1ull << 16;
-constexpr uint32_t kGraphRounds = 4;   // even: the next-round tasks end in C->next
-static_assert(kGraphRounds % 2 == 0, "the task lists alternate between rounds");
+constexpr uint32_t kGraphMaxRounds = 4;
+constexpr uint32_t kGraphFirstRounds = 2;   // hint for a class's first batch
 
 uint64_t pow2_ge(uint64_t x)
 {
@@ -596,8 +789,7 @@ struct Caps {
     uint64_t tasks, chunks, buckets, entries, samples, blocks, leafs, models, max_sample;
     // over the whole replay
     uint64_t groups[kGroupClasses], fills;
-    // pinned staging: control block, tasks, jobs, groups of each class
-    size_t off_tasks, off_jobs, off_groups[kGroupClasses], stage_bytes;
+    StageLayout stage;   // round-0 lists: tasks0 tasks and jobs, `arrays` groups per class
 };
 
 Caps graph_caps(uint64_t keys, uint64_t arrays, const Params& P)
@@ -632,20 +824,12 @@ Caps graph_caps(uint64_t keys, uint64_t arrays, const Params& P)
     // the small arrays of round 0
     const uint64_t fill_min = std::max<uint64_t>(P.base / 8, 2);
     const uint64_t g0 = std::min<uint64_t>(K.buckets, 3 * (N / T) + N / fill_min + 2 * K.tasks + 2) + 1;
-    K.groups[0] = arrays + kGraphRounds * g0;
-    K.groups[1] = arrays + kGraphRounds * (N / (kGroupClassCap[0] + 1) + 1);
-    K.groups[2] = arrays + kGraphRounds * (N / (kGroupClassCap[1] + 1) + 1);
-    K.fills = kGraphRounds * (std::min<uint64_t>(K.buckets, N / fill_min) + N / kFillPiece + 1);
-    size_t off = (sizeof(RoundCtl) + 255) & ~(size_t)255;
-    K.off_tasks = off;
-    off += K.tasks0 * sizeof(Task);
-    K.off_jobs = off;
-    off += K.tasks0 * sizeof(ModelJob);
-    for (uint32_t c = 0; c < kGroupClasses; ++c) {
-        K.off_groups[c] = off;
-        off += arrays * sizeof(Group);
-    }
-    K.stage_bytes = off;
+    K.groups[0] = arrays + kGraphMaxRounds * g0;
+    K.groups[1] = arrays + kGraphMaxRounds * (N / (kGroupClassCap[0] + 1) + 1);
+    K.groups[2] = arrays + kGraphMaxRounds * (N / (kGroupClassCap[1] + 1) + 1);
+    K.fills = kGraphMaxRounds * (std::min<uint64_t>(K.buckets, N / fill_min) + N / kFillPiece + 1);
+    const uint64_t ga[kGroupClasses] = {arrays, arrays, arrays};
+    K.stage = stage_layout(K.tasks0, K.tasks0, ga);
     return K;
 }
 
@@ -667,12 +851,14 @@ ls_status size_for_graph(ls_ctx* C, const Caps& K, hipStream_t st)
     TRY(ensure(C, C->models, (K.gmodels + K.models) * sizeof(double), st));
     TRY(ensure(C, C->sample, std::max(K.gsamples, K.samples) * 8, st));
     TRY(ensure(C, C->sample2, std::max(K.gsamples, K.samples) * 8, st));
-    DevBuf* tabs[2] = {&C->tbest, &C->tfirst};
-    for (DevBuf* t : tabs) {
-        const void* before = t->p;
-        TRY(ensure(C, *t, std::max(K.gleafs, K.leafs) * 8, st));
-        if (t->p != before)
-            HIPCHECK(C, hipMemsetAsync(t->p, 0, t->cap, st));
+    DevBuf* tabs[3] = {&C->tbest, &C->tfirst, &C->tnf};
+    const size_t need[3] = {std::max(K.gleafs, K.leafs) * 8, std::max(K.gleafs, K.leafs) * 8,
+                            std::max(K.tasks0, K.tasks) * 16};
+    for (int i = 0; i < 3; ++i) {
+        const void* before = tabs[i]->p;
+        TRY(ensure(C, *tabs[i], need[i], st));
+        if (tabs[i]->p != before)
+            HIPCHECK(C, hipMemsetAsync(tabs[i]->p, 0, tabs[i]->cap, st));
     }
     TRY(ensure(C, C->cnt, K.entries * 4, st));
     TRY(ensure(C, C->pos, K.entries * 8, st));
@@ -684,7 +870,7 @@ ls_status size_for_graph(ls_ctx* C, const Caps& K, hipStream_t st)
     for (uint32_t c = 0; c < kGroupClasses; ++c)
         TRY(ensure(C, C->groups[c], K.groups[c] * sizeof(Group), st));
     TRY(ensure(C, C->fills, K.fills * sizeof(Fill), st));
-    TRY(ensure_pinned(C, C->gstage, K.stage_bytes, st));
+    TRY(ensure_pinned(C, C->gstage, K.stage.bytes, st));
     return LS_OK;
 }
 
@@ -707,25 +893,20 @@ LayoutParams graph_layout_params(ls_ctx* C, const Caps& K, const Params& P)
 }
 
 // The launches of one replay, recorded on the capture stream.
-ls_status record_graph(ls_ctx* C, const Caps& K, const Params& P, hipStream_t cs)
+ls_status record_graph(ls_ctx* C, const Caps& K, const Params& P, uint32_t rounds, hipStream_t cs)
 {
     RoundCtl* ctl = (RoundCtl*)C->ctl.p;
     const LiveCounts* live = &ctl->cur;
-    const char* sp = (const char*)C->gstage.p;
-    HIPCHECK(C, hipMemcpyAsync(ctl, sp, sizeof(RoundCtl), hipMemcpyHostToDevice, cs));
-    HIPCHECK(C, hipMemcpyAsync(C->next.p, sp + K.off_tasks, K.tasks0 * sizeof(Task), hipMemcpyHostToDevice, cs));
-    HIPCHECK(C, hipMemcpyAsync(C->gjobs.p, sp + K.off_jobs, K.tasks0 * sizeof(ModelJob), hipMemcpyHostToDevice, cs));
-    for (uint32_t c = 0; c < kGroupClasses; ++c)
-        HIPCHECK(C, hipMemcpyAsync(C->groups[c].p, sp + K.off_groups[c], K.arrays * sizeof(Group),
-                                   hipMemcpyHostToDevice, cs));
+    HIPCHECK(C, launch_upload(upload_plan(C, C->gstage, K.stage), cs));
     uint64_t* sample = (uint64_t*)C->sample.p;
     uint64_t* sample2 = (uint64_t*)C->sample2.p;
     uint64_t* tbest = (uint64_t*)C->tbest.p;
     uint64_t* tfirst = (uint64_t*)C->tfirst.p;
+    uint64_t* tnf = (uint64_t*)C->tnf.p;
     double* models = (double*)C->models.p;
     // global models: the host put their counts in ctl->cur
     HIPCHECK(C, launch_train((const ModelJob*)C->gjobs.p, (uint32_t)K.tasks0, (uint32_t)K.gblocks, K.gsamples,
-                             K.gmax_sample, sample, sample2, tbest, tfirst, models, live, cs));
+                             K.gmax_sample, sample, sample2, tbest, tfirst, tnf, models, live, cs));
     const LayoutParams lp = graph_layout_params(C, K, P);
     HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp, ctl, C->d_h_ctl, cs));
     Task* lists[2] = {(Task*)C->next.p, (Task*)C->tasks.p};
@@ -733,13 +914,17 @@ ls_status record_graph(ls_ctx* C, const Caps& K, const Params& P, hipStream_t cs
     for (uint32_t c = 0; c < kGroupClasses; ++c)
         gl.g[c] = (Group*)C->groups[c].p;
     const uint32_t flags = P.flags & LS_FLAG_NONMONOTONE;
-    for (uint32_t r = 0; r < kGraphRounds; ++r) {
+    for (uint32_t r = 0; r < rounds; ++r) {
         Task* in = lists[r & 1];
         Task* out = lists[(r + 1) & 1];
         const uint32_t nt = (uint32_t)(r == 0 ? K.tasks0 : K.tasks);
         HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, K.buckets, ctl, true, cs));
-        HIPCHECK(C, launch_train((const ModelJob*)C->ljobs.p, (uint32_t)K.tasks, (uint32_t)K.blocks, K.samples,
-                                 K.max_sample, sample, sample2, tbest, tfirst, models, live, cs));
+        // local models: the tasks of the first two rounds use the arrays'
+        // global models (levels 0 and 1 of Alg. 2), later ones their own
+        if (r >= 2)
+            HIPCHECK(C, launch_train((const ModelJob*)C->ljobs.p, (uint32_t)K.tasks, (uint32_t)K.blocks,
+                                     K.samples, K.max_sample, sample, sample2, tbest, tfirst, tnf, models, live,
+                                     cs));
         HIPCHECK(C, launch_hist(in, nt, (uint32_t)K.chunks, 0, models, (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p,
                                 (uint16_t*)C->ids.p, P.fanout, P.leaves, flags, live, cs));
         HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, K.entries, (uint64_t*)C->scantmp.p,
@@ -756,20 +941,20 @@ ls_status record_graph(ls_ctx* C, const Caps& K, const Params& P, hipStream_t cs
     for (uint32_t c = 0; c < kGroupClasses; ++c)
         gmax[c] = (uint32_t)std::min<uint64_t>(lp.cap_groups[c], 0xffffffffu);
     const uint32_t fmax = (uint32_t)std::min<uint64_t>(lp.cap_fills, 0xffffffffu);
-    HIPCHECK(C, launch_base(gl, gmax, ctl, cs));
-    HIPCHECK(C, launch_fill((const Fill*)C->fills.p, fmax, ctl, cs));
+    TRY(launch_finish_lists(C, gl, gmax, (const Fill*)C->fills.p, fmax, ctl, cs));
     HIPCHECK(C, launch_touchup(gl, gmax, (const Fill*)C->fills.p, fmax, 0, ctl, true, cs));
     HIPCHECK(C, hipMemcpyAsync(C->h_ctl, ctl, sizeof(RoundCtl), hipMemcpyDeviceToHost, cs));
     return LS_OK;
 }
 
-ls_status capture_graph(ls_ctx* C, const Caps& K, const Params& P, hipGraphExec_t* out)
+ls_status capture_graph(ls_ctx* C, const Caps& K, const Params& P, uint32_t rounds, hipGraphExec_t* out)
 {
     if (!C->cap_stream)
         HIPCHECK(C, hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
     hipStream_t cs = C->cap_stream;
-    HIPCHECK(C, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    ls_status rc = record_graph(C, K, P, cs);
+    GateCapture gate;
+    HIPCHECK(C, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    ls_status rc = record_graph(C, K, P, rounds, cs);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc == LS_OK && e != hipSuccess)
@@ -812,52 +997,51 @@ ls_status run_graph(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const
     if (B.tasks.size() > K.tasks0 || B.tr.samples > K.gsamples || B.tr.blocks > K.gblocks ||
         B.tr.max_sample > K.gmax_sample || B.tr.leaves > K.gleafs || B.tr.models > K.gmodels)
         return fail(C, LS_ERR_HIP, "batch exceeds the bounds of its graph class");
+    // rounds in the replay: none without a round-0 task, else as many as
+    // the class's last batch needed
+    RoundsHint* H = nullptr;
+    for (auto& h : C->hints)
+        if (h.keys == ckeys && h.arrays == carrays && same_params(h.P, P))
+            H = &h;
+    const uint32_t rounds = B.tasks.empty() ? 0u : (H ? H->rounds : kGraphFirstRounds);
     GraphEntry* G = nullptr;
     for (auto& e : C->graphs)
-        if (e.keys == ckeys && e.arrays == carrays && e.gen == C->gen && same_params(e.P, P))
+        if (e.keys == ckeys && e.arrays == carrays && e.rounds == rounds && e.gen == C->gen && same_params(e.P, P))
             G = &e;
     if (!G) {
         TRY(size_for_graph(C, K, st));
         drop_graphs(C, false);
-        GraphEntry e{ckeys, carrays, C->gen, P, nullptr, C->next.p};
-        TRY(capture_graph(C, K, P, &e.exec));
+        void* lists[2] = {C->next.p, C->tasks.p};
+        GraphEntry e{ckeys, carrays, C->gen, P, rounds, nullptr, lists[rounds & 1]};
+        TRY(capture_graph(C, K, P, rounds, &e.exec));
         C->graphs.push_back(e);
         G = &C->graphs.back();
     }
-    // Host-driven rounds swap the two task lists without reallocating them,
-    // so since the capture they may have traded places: the continuation
-    // below expects the replay's last next-round list in C->next.
-    if (C->next.p != G->list0) {
-        if (C->tasks.p != G->list0)
-            return fail(C, LS_ERR_HIP, "graph task lists out of step with the context");
-        std::swap(C->tasks, C->next);
-    }
-    // the replay's uploads read the staging area
-    char* sp = (char*)C->gstage.p;
-    RoundCtl* c0 = (RoundCtl*)sp;
-    std::memset(c0, 0, sizeof(RoundCtl));
-    c0->ntasks = (uint32_t)B.tasks.size();
-    for (uint32_t c = 0; c < kGroupClasses; ++c) {
-        c0->ngroups[c] = (uint32_t)B.groups0[c].size();
-        if (!B.groups0[c].empty())
-            std::memcpy(sp + K.off_groups[c], B.groups0[c].data(), B.groups0[c].size() * sizeof(Group));
-    }
-    c0->cur.njobs = (uint32_t)B.tr.jobs.size();
-    c0->cur.blocks = B.tr.blocks;
-    c0->cur.samples = B.tr.samples;
-    c0->cur.max_sample = B.tr.max_sample;
-    if (!B.tasks.empty())
-        std::memcpy(sp + K.off_tasks, B.tasks.data(), B.tasks.size() * sizeof(Task));
-    if (!B.tr.jobs.empty())
-        std::memcpy(sp + K.off_jobs, B.tr.jobs.data(), B.tr.jobs.size() * sizeof(ModelJob));
+    // the replay's upload kernel reads the staging area
+    fill_stage((unsigned char*)C->gstage.p, K.stage, B);
     HIPCHECK(C, hipGraphLaunch(G->exec, st));
     HIPCHECK(C, hipStreamSynchronize(st));
     TRY(check_overflow(C));
+    // Host-driven rounds swap the two task lists without reallocating them,
+    // so since the capture they may have traded places: the continuation
+    // expects the replay's last next-round list in C->next.
+    if (C->next.p != G->list_final) {
+        if (C->tasks.p != G->list_final)
+            return fail(C, LS_ERR_HIP, "graph task lists out of step with the context");
+        std::swap(C->tasks, C->next);
+    }
     if (C->h_ctl->ntasks) {
         // more rounds than the replay holds: continue from its state
         Prof prof{C, st, false, {}};
         TRY(rounds_eager(C, st, P, layout_params(P, K.gmodels), P.flags & LS_FLAG_NONMONOTONE, prof));
         TRY(finish_eager(C, st, P, prof, B.group0_keys));
+    }
+    if (!B.tasks.empty()) {
+        const uint32_t need = std::min(std::max<uint32_t>(C->h_ctl->rounds, 1), kGraphMaxRounds);
+        if (H)
+            H->rounds = need;
+        else
+            C->hints.push_back(RoundsHint{ckeys, carrays, P, need});
     }
     return LS_OK;
 }
@@ -883,23 +1067,20 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
     const uint64_t global_models = B.tr.models;
     Prof prof{C, st, (P.flags & LS_FLAG_PROFILE) != 0, {}};
 
-    std::memset(C->h_ctl_init, 0, sizeof(RoundCtl));
-    C->h_ctl_init->ntasks = (uint32_t)B.tasks.size();
-    for (uint32_t c = 0; c < kGroupClasses; ++c) {
-        C->h_ctl_init->ngroups[c] = (uint32_t)B.groups0[c].size();
+    // round-0 lists: staged in mapped host memory, copied by one kernel
+    const uint64_t ng0[kGroupClasses] = {B.groups0[0].size(), B.groups0[1].size(), B.groups0[2].size()};
+    const StageLayout SL = stage_layout(B.tasks.size(), B.tr.jobs.size(), ng0);
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
         TRY(ensure(C, C->groups[c], std::max<size_t>(B.groups0[c].size(), 1) * sizeof(Group), st));
-        TRY(upload(C, C->pin_groups[c], C->groups[c], B.groups0[c], st));
-    }
-    HIPCHECK(C, hipMemcpyAsync(C->ctl.p, C->h_ctl_init, sizeof(RoundCtl), hipMemcpyHostToDevice, st));
     TRY(ensure(C, C->next, std::max<size_t>(B.tasks.size(), 1) * sizeof(Task), st));
     TRY(ensure(C, C->ljobs, std::max<size_t>(B.tasks.size(), 1) * sizeof(ModelJob), st));
-    TRY(upload(C, C->pin_tasks, C->next, B.tasks, st));
-    if (!B.tr.jobs.empty()) {
-        TRY(ensure(C, C->gjobs, B.tr.jobs.size() * sizeof(ModelJob), st));
-        TRY(upload(C, C->pin_jobs, C->gjobs, B.tr.jobs, st));
+    TRY(ensure(C, C->gjobs, std::max<size_t>(B.tr.jobs.size(), 1) * sizeof(ModelJob), st));
+    TRY(ensure_pinned(C, C->estage, SL.bytes, st));
+    fill_stage((unsigned char*)C->estage.p, SL, B);
+    HIPCHECK(C, launch_upload(upload_plan(C, C->estage, SL), st));
+    if (!B.tr.jobs.empty())
         TRY(train(C, C->gjobs, (uint32_t)B.tr.jobs.size(), B.tr.blocks, B.tr.samples, B.tr.leaves,
                   B.tr.max_sample, 0, B.tr.models, st, &prof));
-    }
     const LayoutParams lp = layout_params(P, global_models);
     if (!B.tasks.empty()) {
         HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp, (RoundCtl*)C->ctl.p, C->d_h_ctl,
@@ -917,6 +1098,7 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
 
 ls_status sort_arrays(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const ls_params* p)
 {
+    GateUse gate;
     Params P;
     TRY(resolve(C, p, P));
     for (auto& a : arrays) {
@@ -954,6 +1136,7 @@ void ls_default_params(ls_params* p)
 
 ls_status ls_create(ls_ctx** out, int device)
 {
+    GateUse gate;
     if (!out)
         return LS_ERR_INVALID;
     *out = nullptr;
@@ -971,8 +1154,7 @@ ls_status ls_create(ls_ctx** out, int device)
         C->lds_limit = prop.sharedMemPerBlock;
     if (hipHostMalloc((void**)&C->h_ctl, sizeof(RoundCtl), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||
-        hipHostGetDevicePointer((void**)&C->d_h_ctl, C->h_ctl, 0) != hipSuccess ||
-        hipHostMalloc((void**)&C->h_ctl_init, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess) {
+        hipHostGetDevicePointer((void**)&C->d_h_ctl, C->h_ctl, 0) != hipSuccess) {
         delete C;
         return LS_ERR_NOMEM;
     }
@@ -982,31 +1164,37 @@ ls_status ls_create(ls_ctx** out, int device)
 
 ls_status ls_destroy(ls_ctx* C)
 {
+    GateUse gate;
     if (!C)
         return LS_ERR_INVALID;
     (void)hipSetDevice(C->device);
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&C->scratch, &C->tune, &C->ids, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst, &C->gjobs,
+    DevBuf* bufs[] = {&C->scratch, &C->tune, &C->ids, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst,
+                      &C->tnf, &C->gjobs,
                       &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
                       &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2]};
     for (DevBuf* b : bufs)
         if (b->p)
             (void)hipFree(b->p);
-    PinBuf* pins[] = {&C->pin_tasks, &C->pin_jobs, &C->pin_groups[0], &C->pin_groups[1], &C->pin_groups[2]};
+    PinBuf* pins[] = {&C->pin_jobs, &C->estage, &C->gstage};
     for (PinBuf* b : pins)
         if (b->p)
             (void)hipHostFree(b->p);
     if (C->h_ctl)
         (void)hipHostFree(C->h_ctl);
-    if (C->h_ctl_init)
-        (void)hipHostFree(C->h_ctl_init);
     for (hipEvent_t e : C->ev_pool)
         (void)hipEventDestroy(e);
     drop_graphs(C, true);
-    if (C->gstage.p)
-        (void)hipHostFree(C->gstage.p);
     if (C->cap_stream)
         (void)hipStreamDestroy(C->cap_stream);
+    for (int i = 0; i < 2; ++i) {
+        if (C->side[i])
+            (void)hipStreamDestroy(C->side[i]);
+        if (C->ev_join[i])
+            (void)hipEventDestroy(C->ev_join[i]);
+    }
+    if (C->ev_fork)
+        (void)hipEventDestroy(C->ev_fork);
     delete C;
     return LS_OK;
 }
@@ -1027,6 +1215,7 @@ ls_status ls_workspace_size(ls_ctx* C, ls_dtype dtype, size_t n, const ls_params
 
 ls_status ls_reserve(ls_ctx* C, size_t n, const ls_params* p)
 {
+    GateUse gate;
     if (!C)
         return LS_ERR_INVALID;
     Params P;
@@ -1092,6 +1281,7 @@ ls_status ls_sort_arrays(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_s
 ls_status ls_autotune(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_stream_t stream, const ls_params* base,
                       uint32_t reps, ls_params* best, ls_tune_result* results, size_t cap, size_t* n_results)
 {
+    GateUse gate;
     if (!C || !best || (count && !h_arrays))
         return LS_ERR_INVALID;
     ls_params bp;
@@ -1204,6 +1394,7 @@ ls_status ls_autotune(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_stre
 
 ls_status ls_sync(ls_ctx* C, uint32_t* device_status)
 {
+    GateUse gate;
     if (!C)
         return LS_ERR_INVALID;
     HIPCHECK(C, hipSetDevice(C->device));
@@ -1267,6 +1458,7 @@ const char* ls_last_error(ls_ctx* C)
 ls_status ls_model_train(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n, const ls_params* p,
                          double* h_model_out, size_t cap)
 {
+    GateUse gate;
     if (!C || !d_keys || !n || !h_model_out || (dtype != LS_F64 && dtype != LS_U64))
         return LS_ERR_INVALID;
     Params P;
@@ -1304,6 +1496,7 @@ ls_status ls_stage_hist(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n,
                         uint32_t leaves, double scale, int64_t offset, uint32_t fanout, uint64_t* h_counts,
                         uint64_t* h_min, uint64_t* h_max)
 {
+    GateUse gate;
     if (!C || !d_keys || !n || !h_model || !h_counts || (dtype != LS_F64 && dtype != LS_U64))
         return LS_ERR_INVALID;
     if (leaves < 1 || leaves > kMaxLeaves || fanout < 2 || fanout > kMaxFanout)

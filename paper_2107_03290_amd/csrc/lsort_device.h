@@ -337,6 +337,72 @@ __device__ inline uint32_t block_scan_u32(uint32_t* a, uint32_t n, uint32_t* wsu
     return block_scan_u32(a, a, n, wsum);
 }
 
+// K exclusive scans of a[k][0..n) in place (LDS, u32) sharing the three
+// barriers of one; totals[k] receives each grand total.  wsum: K rows of
+// blockDim/64 + 1 entries; at most 16 waves.
+template <uint32_t K>
+__device__ inline void block_scan_u32_multi(uint32_t* const (&a)[K], uint32_t n, uint32_t (*wsum)[17],
+                                            uint32_t (&totals)[K])
+{
+    const uint32_t nt = blockDim.x;
+    const uint32_t per = (n + nt - 1) / nt;
+    const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    uint32_t s[K], x[K];
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k) {
+        s[k] = 0;
+        for (uint32_t i = lo; i < hi; ++i)
+            s[k] += a[k][i];
+        x[k] = s[k];
+#pragma unroll
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x[k], d, 64);
+            if (lane >= d)
+                x[k] += y;
+        }
+        if (lane == 63)
+            wsum[k][wave] = x[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k)
+        wave_totals_scan<uint32_t>(wsum[k], nt / 64, 0u, AddU32());
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k) {
+        uint32_t base = wsum[k][wave] + x[k] - s[k];
+        for (uint32_t i = lo; i < hi; ++i) {
+            const uint32_t v = a[k][i];
+            a[k][i] = base;
+            base += v;
+        }
+        totals[k] = wsum[k][nt / 64];
+    }
+    __syncthreads();
+}
+
+// Sum / maximum over the 64 lanes of a wave (every lane gets the result).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (uint32_t d = 32; d > 0; d >>= 1)
+        v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (uint32_t d = 32; d > 0; d >>= 1) {
+        const T y = __shfl_xor(v, d, 64);
+        v = y > v ? y : v;
+    }
+    return v;
+}
+
 // Generic exclusive block scan (LDS, in place) with an associative operator;
 // returns the reduction of all n entries.  wsum: blockDim/64 + 1 entries.
 template <typename T, typename Op>

@@ -49,17 +49,18 @@ constexpr uint32_t kPersistBase[kGroupClasses] = {2048, 1024, 512};
 constexpr uint32_t kPersistFill = 2048;
 constexpr uint32_t kPersistTouch = 1024;
 
-hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, const RoundCtl* gctl, hipStream_t st)
+hipError_t launch_base(const Group* groups, uint32_t ngroups, uint32_t cls, const RoundCtl* gctl, hipStream_t st)
 {
-    uint32_t grid[kGroupClasses];
-    for (uint32_t c = 0; c < kGroupClasses; ++c)
-        grid[c] = gctl ? std::min(ngroups[c], kPersistBase[c]) : ngroups[c];
-    if (grid[0])
-        k_base<64><<<grid[0], 64, (size_t)base_pad(kGroupClassCap[0]) * 8, st>>>(groups.g[0], ngroups[0], gctl, 0);
-    if (grid[1])
-        k_base<256><<<grid[1], 256, (size_t)base_pad(kGroupClassCap[1]) * 8, st>>>(groups.g[1], ngroups[1], gctl, 1);
-    if (grid[2])
-        k_base<512><<<grid[2], 512, (size_t)base_pad(kGroupClassCap[2]) * 8, st>>>(groups.g[2], ngroups[2], gctl, 2);
+    const uint32_t grid = gctl ? std::min(ngroups, kPersistBase[cls]) : ngroups;
+    if (!grid)
+        return hipSuccess;
+    const size_t lds = (size_t)base_pad(kGroupClassCap[cls]) * 8;
+    switch (cls) {
+    case 0: k_base<64><<<grid, 64, lds, st>>>(groups, ngroups, gctl, 0); break;
+    case 1: k_base<256><<<grid, 256, lds, st>>>(groups, ngroups, gctl, 1); break;
+    case 2: k_base<512><<<grid, 512, lds, st>>>(groups, ngroups, gctl, 2); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ constexpr uint32_t kMaxBase = 8192;        // largest group the LDS base case so
 constexpr uint32_t kNoPrev = 0xffffu;      // "no knot below": F = 0
 constexpr uint64_t kFillPiece = 1u << 16;  // keys per fill work item
 constexpr uint32_t kTargetChunks = 2048;   // chunks per partition round (8 per CU)
+constexpr uint32_t kSmallRoundChunks = 256; // chunks of a small round (one per CU)
 constexpr uint32_t kLocalMinSample = 1024; // smallest sample of a local model
 constexpr uint32_t kSampleBlock = 4096;    // sample keys per training block (one LDS-sorted run)
 constexpr uint32_t kGroupClasses = 3;      // base-case size classes: <= 1024, 4096, 8192 keys
@@ -148,6 +149,10 @@ struct RoundCtl {
     LiveCounts cur;                   // graph mode: the running round's sizes
 };
 
+static_assert(sizeof(RoundCtl) % 8 == 0 && sizeof(Task) % 8 == 0 && sizeof(ModelJob) % 8 == 0 &&
+                  sizeof(Group) % 8 == 0,
+              "the control block is published, and the round-0 lists uploaded, as 8-byte words");
+
 // Device model layout (doubles): header [xmin, xmax, rs, m'], then for the
 // L leaf knots and the start knot (index L): {X, ylo, s, yhi} each; then the
 // L + 1 mid-ranks ym, the L + 1 values y and y1 (kept for export only), and L
@@ -194,18 +199,34 @@ __host__ __device__ inline uint32_t child_fanout(uint64_t n, uint32_t thresh, ui
     return f > cap ? cap : f;
 }
 
+// Round-0 lists staged in pinned, device-mapped host memory: the control
+// block at offset 0, then the tasks, the global training jobs and the groups
+// of each size class at the given offsets.  The counts are the staged control
+// block's (ntasks, cur.njobs, ngroups).
+struct UploadPlan {
+    const unsigned char* stage;   // device address of the staging area
+    RoundCtl* ctl;
+    Task* tasks;
+    ModelJob* jobs;
+    Group* groups[kGroupClasses];
+    uint64_t off_tasks, off_jobs, off_groups[kGroupClasses];
+};
+
 // Kernel launchers.
+// Copy the staged round-0 lists to the device (one launch, any counts).
+hipError_t launch_upload(const UploadPlan& U, hipStream_t st);
 // Train njobs models: gather each job's sample, sort it (runs of
 // kSampleBlock in LDS, then merge passes between d_sample and d_tmp), find
-// each leaf's most repeated value and fit.  d_best / d_first: per-leaf tables
-// that start and end at zero.
+// each leaf's most repeated value and fit.  d_best / d_first: per-leaf
+// tables, d_nf: two counts per job; all start and end at zero.
 // total: sample words of all jobs.  live (graph mode, may be null): njobs,
 // total_blocks and total are upper bounds and the real counts are read from
 // live (njobs, blocks, samples); max_sample, a bound on one job's sample,
 // fixes the merge passes (extra passes copy whole runs).
 hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t total,
                         uint64_t max_sample, uint64_t* d_sample, uint64_t* d_tmp, uint64_t* d_best,
-                        uint64_t* d_first, double* d_models, const LiveCounts* live, hipStream_t st);
+                        uint64_t* d_first, uint64_t* d_nf, double* d_models, const LiveCounts* live,
+                        hipStream_t st);
 // snapshot (graph mode): copy the next-round sizes into ctl->cur first and
 // clear ctl->buckets entries (nbuckets is then the grid's upper bound).
 hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, bool snapshot, hipStream_t st);
@@ -241,7 +262,8 @@ hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_c
 // while gctl->ntasks says partition rounds are still pending or after an
 // overflow.
 // In graph mode the grids are capped and the workgroups stride over the lists.
-hipError_t launch_base(GroupLists groups, const uint32_t* ngroups, const RoundCtl* gctl, hipStream_t st);
+// One size class (cls) of base-case groups.
+hipError_t launch_base(const Group* groups, uint32_t ngroups, uint32_t cls, const RoundCtl* gctl, hipStream_t st);
 hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, const RoundCtl* gctl, hipStream_t st);
 hipError_t launch_touchup(GroupLists groups, const uint32_t* ngroups, const Fill* d_fills, uint32_t nfill,
                           int full, RoundCtl* d_ctl, bool graph, hipStream_t st);

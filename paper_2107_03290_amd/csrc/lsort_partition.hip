@@ -58,6 +58,44 @@ hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_c
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- upload --
+
+// The staged counts are read over the bus by every workgroup; the words of
+// all lists are then copied grid-stride.
+__global__ __launch_bounds__(256) void k_upload(UploadPlan U)
+{
+    const RoundCtl* c0 = reinterpret_cast<const RoundCtl*>(U.stage);
+    uint64_t end[3 + kGroupClasses];
+    const uint64_t nctl = sizeof(RoundCtl) / 8;
+    end[0] = nctl;
+    end[1] = end[0] + (uint64_t)c0->ntasks * (sizeof(Task) / 8);
+    end[2] = end[1] + (uint64_t)c0->cur.njobs * (sizeof(ModelJob) / 8);
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        end[3 + c] = end[2 + c] + (uint64_t)c0->ngroups[c] * (sizeof(Group) / 8);
+    const uint64_t* w = reinterpret_cast<const uint64_t*>(U.stage);
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < end[2 + kGroupClasses];
+         i += (uint64_t)gridDim.x * 256) {
+        if (i < end[0]) {
+            reinterpret_cast<uint64_t*>(U.ctl)[i] = w[i];
+        } else if (i < end[1]) {
+            reinterpret_cast<uint64_t*>(U.tasks)[i - end[0]] = w[U.off_tasks / 8 + (i - end[0])];
+        } else if (i < end[2]) {
+            reinterpret_cast<uint64_t*>(U.jobs)[i - end[1]] = w[U.off_jobs / 8 + (i - end[1])];
+        } else {
+            uint32_t c = 0;
+            while (i >= end[3 + c])
+                ++c;
+            reinterpret_cast<uint64_t*>(U.groups[c])[i - end[2 + c]] = w[U.off_groups[c] / 8 + (i - end[2 + c])];
+        }
+    }
+}
+
+hipError_t launch_upload(const UploadPlan& U, hipStream_t st)
+{
+    k_upload<<<16, 256, 0, st>>>(U);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- histogram --
 
 // Bucket sizes per (bucket, chunk) plus per-bucket min/max of the key words
@@ -268,17 +306,29 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
         if (tasks[i].kind == kGlobal || tasks[i].kind == kGlobalL1)
             maxl = max(maxl, tasks[i].leaves);
     }
-    atomicAdd(&s_keys, mykeys);
-    atomicMax(&s_maxf, maxf);
-    atomicMax(&s_maxl, maxl);
-    atomicMax(&s_maxlev, maxlev);
+    // one LDS atomic per wave: same-address atomics serialise lane by lane
+    mykeys = wave_sum(mykeys);
+    maxf = wave_max(maxf);
+    maxl = wave_max(maxl);
+    maxlev = wave_max(maxlev);
+    if ((threadIdx.x & 63u) == 0) {
+        atomicAdd(&s_keys, mykeys);
+        atomicMax(&s_maxf, maxf);
+        atomicMax(&s_maxl, maxl);
+        atomicMax(&s_maxlev, maxlev);
+    }
     __syncthreads();
     const uint64_t nkeys = s_keys;
+    // at most kTargetChunks chunks; a small round gets about one chunk per
+    // CU, of one to four tiles
     uint64_t chunk = (nkeys + kTargetChunks - 1) / kTargetChunks;
+    uint64_t small = (nkeys + kSmallRoundChunks - 1) / kSmallRoundChunks;
+    small = small < lp.tile ? lp.tile : (small > 4ull * lp.tile ? 4ull * lp.tile : small);
+    chunk = chunk > small ? chunk : small;
     chunk = (chunk + lp.tile - 1) / lp.tile * lp.tile;
-    chunk = chunk < 4ull * lp.tile ? 4ull * lp.tile : chunk;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     uint32_t my_maxl = 1;
+    unsigned long long my_maxm = 0;
     for (uint32_t base = 0; base < nt; base += NT) {
         const uint32_t i = base + threadIdx.x;
         const bool valid = i < nt;
@@ -300,7 +350,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
             const uint64_t want_l = m / 8 ? m / 8 : 1;
             L = (uint32_t)(want_l < lp.leaves ? want_l : lp.leaves);
             my_maxl = max(my_maxl, L);
-            atomicMax(&s_maxm, (unsigned long long)m);
+            my_maxm = max(my_maxm, (unsigned long long)m);
         }
         const uint64_t nch = valid ? (T.n + chunk - 1) / chunk : 0;
         uint64_t q[kLayoutQ] = {nch,
@@ -368,7 +418,12 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
         }
         __syncthreads();
     }
-    atomicMax(&s_maxl, my_maxl);
+    my_maxl = wave_max(my_maxl);
+    my_maxm = wave_max(my_maxm);
+    if (lane == 0) {
+        atomicMax(&s_maxl, my_maxl);
+        atomicMax(&s_maxm, my_maxm);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const bool over = ctl->overflow || nkeys > lp.cap_keys || carry[0] > lp.cap_chunks ||
@@ -402,9 +457,16 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
         }
         ctl->deepest = max(ctl->deepest, s_maxlev);
         __threadfence();
-        *host_ctl = *ctl;      // publish to the host without a copy
-        __threadfence_system();
     }
+    __syncthreads();
+    // publish to the host without a copy: one word per lane, read from L2
+    // (other workgroups added to the counters with atomics)
+    constexpr uint32_t kWords = sizeof(RoundCtl) / 8;
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(ctl);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(host_ctl);
+    for (uint32_t i = threadIdx.x; i < kWords; i += NT)
+        dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence_system();
 }
 
 __global__ __launch_bounds__(256) void k_layout(Task* tasks, ModelJob* jobs, LayoutParams lp, RoundCtl* ctl,
@@ -445,7 +507,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
     uint32_t* tidx = cidx[1] + f;
     uint32_t* fidx = tidx + f;
     uint8_t* kind = reinterpret_cast<uint8_t*>(fidx + f);
-    __shared__ uint32_t ws_u[17];
+    __shared__ uint32_t ws_m[5][17];
     __shared__ int32_t ws_i[17];
     __shared__ uint32_t s_gb[kGroupClasses], s_tb, s_fb, s_noprog, s_nfb, s_over;
     __shared__ unsigned long long s_fkeys, s_gkeys;
@@ -481,6 +543,8 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
     }
     __syncthreads();
     block_scan_op<int32_t>(prv, f, -1, MaxI32(), ws_i);      // prv[b]: last non-empty bucket before b
+    unsigned long long my_fkeys = 0, my_gkeys = 0;
+    uint32_t my_nfb = 0;
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
         const uint8_t k = kind[b];
         bool lead = k == kSolo;
@@ -496,11 +560,23 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
         if (sz == T.n && (k == kBig || k == kFillB))
             s_noprog = 1;
         if (k == kFillB) {
-            atomicAdd(&s_fkeys, (unsigned long long)sz);
-            atomicAdd(&s_nfb, 1u);
+            my_fkeys += sz;
+            ++my_nfb;
         }
         if (k == kSmall || k == kSolo)
-            atomicAdd(&s_gkeys, (unsigned long long)sz);
+            my_gkeys += sz;
+    }
+    // one LDS atomic per wave
+    my_fkeys = wave_sum(my_fkeys);
+    my_gkeys = wave_sum(my_gkeys);
+    my_nfb = wave_sum(my_nfb);
+    if ((threadIdx.x & 63u) == 0) {
+        if (my_fkeys)
+            atomicAdd(&s_fkeys, my_fkeys);
+        if (my_gkeys)
+            atomicAdd(&s_gkeys, my_gkeys);
+        if (my_nfb)
+            atomicAdd(&s_nfb, my_nfb);
     }
     __syncthreads();
     // kind[] must only be rewritten once every thread is done reading it
@@ -531,11 +607,12 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
         cidx[2][b] = c2;
     }
     __syncthreads();
-    uint32_t ng[kGroupClasses];
-    for (uint32_t c = 0; c < kGroupClasses; ++c)
-        ng[c] = block_scan_u32(cidx[c], f, ws_u);
-    const uint32_t nt = block_scan_u32(tidx, f, ws_u);
-    const uint32_t nf = block_scan_u32(fidx, f, ws_u);
+    uint32_t* const lists[5] = {cidx[0], cidx[1], cidx[2], tidx, fidx};
+    uint32_t tot[5];
+    block_scan_u32_multi<5>(lists, f, ws_m, tot);
+    const uint32_t ng[kGroupClasses] = {tot[0], tot[1], tot[2]};
+    const uint32_t nt = tot[3];
+    const uint32_t nf = tot[4];
     if (threadIdx.x == 0) {
         for (uint32_t c = 0; c < kGroupClasses; ++c)
             s_gb[c] = ng[c] ? atomicAdd(&ctl->ngroups[c], ng[c]) : 0;

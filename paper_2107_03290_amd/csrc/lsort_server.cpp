@@ -12,11 +12,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -58,6 +60,7 @@ struct ls_server {
     bool stopping = false;
     std::vector<std::thread> workers;
     ls_status fatal = LS_OK;
+    std::string last_error;   // message of the latest failed batch
 };
 
 namespace {
@@ -125,6 +128,8 @@ void worker_main(ls_server* S)
         const auto now = Clock::now();
         {
             std::lock_guard<std::mutex> lk(S->mu);
+            if (status != LS_OK)
+                S->last_error = ok ? ls_last_error(ctx) : "worker start-up failed (context or stream creation)";
             for (auto& r : batch) {
                 ls_status s = status;
                 if (status != LS_OK && batch.size() > 1)
@@ -225,6 +230,17 @@ ls_status ls_server_stats(ls_server* S, uint64_t* out6)
     out6[3] = S->peak;
     out6[4] = S->admitted;
     out6[5] = S->queue.size();
+    return LS_OK;
+}
+
+ls_status ls_server_last_error(ls_server* S, char* buf, size_t cap)
+{
+    if (!S || !buf || !cap)
+        return LS_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(S->mu);
+    const size_t n = std::min(cap - 1, S->last_error.size());
+    std::memcpy(buf, S->last_error.data(), n);
+    buf[n] = 0;
     return LS_OK;
 }
 

@@ -1,7 +1,8 @@
 // Model training on the device (Sec. 6.1: two layers, 1% sample; the
 // procedure itself is reading R14 of the model):
-//   k_train_sample     gather each job's sample as order-preserving words
-//   k_train_sort_runs  sort runs of kSampleBlock words in LDS
+//   k_train_runs       gather each job's sample as order-preserving words in
+//                      runs of kSampleBlock, count its non-finite words, and
+//                      sort each run in LDS
 //   k_train_merge      merge passes: every word moves to its rank in the
 //                      merged pair of runs (its index plus its count in the
 //                      other run), so a pass is one gather-free scatter
@@ -10,6 +11,8 @@
 //   k_train_fit        knots (the most repeated value of a leaf when it holds
 //                      2+ copies and 1/L of the sample, else the leaf's
 //                      smallest value), mid-ranks, segments; tables to zero
+// The per-leaf tables (best, first) and the per-job non-finite counts start
+// and end at zero.
 #include "lsort_device.h"
 
 #pragma clang fp contract(off)
@@ -41,27 +44,12 @@ __device__ __forceinline__ uint32_t find_job_of(const ModelJob* jobs, uint32_t n
     return lo;
 }
 
-// Finite part [lo, hi) of a sorted sample S[0..m): non-finite words sit at
-// both ends (negative ones up to -inf's word, positive ones from +inf's).
-__device__ inline void finite_range(const uint64_t* S, uint64_t m, uint32_t dt, uint64_t& lo, uint64_t& hi)
+// Finite part [lo, hi) of a job's sorted sample: its non-finite words sit
+// at both ends, nf[0] of them up to -inf's word and nf[1] from +inf's.
+__device__ __forceinline__ void finite_range(const uint64_t* nf, uint64_t m, uint64_t& lo, uint64_t& hi)
 {
-    if (dt != kF64) {
-        lo = 0;
-        hi = m;
-        return;
-    }
-    uint64_t a = 0, b = m;
-    while (a < b) {
-        const uint64_t mid = (a + b) >> 1;
-        if (S[mid] <= kOrdNegInf) a = mid + 1; else b = mid;
-    }
-    lo = a;
-    b = m;
-    while (a < b) {
-        const uint64_t mid = (a + b) >> 1;
-        if (S[mid] < kOrdPosInf) a = mid + 1; else b = mid;
-    }
-    hi = a;
+    lo = nf[0];
+    hi = m - nf[1];
 }
 
 // First index in [a, b) whose value exceeds x (values non-decreasing).
@@ -99,39 +87,10 @@ __device__ __forceinline__ uint32_t root_leaf(double x, const Root& R, uint32_t 
     return (uint32_t)t;
 }
 
-// Gather the sample (order-preserving words), 16 independent loads per lane.
-__global__ __launch_bounds__(256) void k_train_sample(const ModelJob* jobs, uint32_t njobs, uint64_t* sample,
-                                                      const LiveCounts* live)
-{
-    if (live) {
-        if (blockIdx.x >= live->blocks)
-            return;
-        njobs = live->njobs;
-    }
-    __shared__ uint32_t s_job;
-    if (threadIdx.x == 0)
-        s_job = find_job(jobs, njobs, blockIdx.x);
-    __syncthreads();
-    const ModelJob J = jobs[s_job];
-    const uint64_t t0 = (uint64_t)(blockIdx.x - J.block0) * kSampleBlock;
-    constexpr uint32_t U = kSampleBlock / 256;
-    uint64_t raw[U];
-#pragma unroll
-    for (uint32_t u = 0; u < U; ++u) {
-        const uint64_t t = t0 + u * 256 + threadIdx.x;
-        raw[u] = t < J.m ? J.src[sample_index(J.seed, t, J.n)] : 0;
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < U; ++u) {
-        const uint64_t t = t0 + u * 256 + threadIdx.x;
-        if (t < J.m)
-            sample[J.sample_off + t] = to_ord(raw[u], J.dtype);
-    }
-}
-
-// Sort the block's run of up to kSampleBlock sample words in LDS.
-__global__ __launch_bounds__(256) void k_train_sort_runs(const ModelJob* jobs, uint32_t njobs, uint64_t* sample,
-                                                         const LiveCounts* live)
+// Gather one run of up to kSampleBlock sample words (16 independent loads
+// per lane) into LDS, count the non-finite ones (f64), sort the run.
+__global__ __launch_bounds__(256) void k_train_runs(const ModelJob* jobs, uint32_t njobs, uint64_t* sample,
+                                                    uint64_t* nf, const LiveCounts* live)
 {
     if (live) {
         if (blockIdx.x >= live->blocks)
@@ -141,10 +100,14 @@ __global__ __launch_bounds__(256) void k_train_sort_runs(const ModelJob* jobs, u
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t* s = reinterpret_cast<uint64_t*>(smem);
     __shared__ uint32_t s_job;
-    if (threadIdx.x == 0)
+    __shared__ uint32_t s_nf[2];
+    if (threadIdx.x == 0) {
         s_job = find_job(jobs, njobs, blockIdx.x);
+        s_nf[0] = s_nf[1] = 0;
+    }
     __syncthreads();
-    const ModelJob J = jobs[s_job];
+    const uint32_t j = s_job;
+    const ModelJob J = jobs[j];
     const uint64_t t0 = (uint64_t)(blockIdx.x - J.block0) * kSampleBlock;
     if (t0 >= J.m)
         return;
@@ -152,11 +115,39 @@ __global__ __launch_bounds__(256) void k_train_sort_runs(const ModelJob* jobs, u
     uint32_t logN = 4;
     while ((1u << logN) < n)
         ++logN;
-    uint64_t* run = sample + J.sample_off + t0;
-    for (uint32_t i = threadIdx.x; i < (1u << logN); i += 256)
-        s[base_pad(i)] = i < n ? run[i] : ~0ull;
+    constexpr uint32_t U = kSampleBlock / 256;
+    uint64_t raw[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t i = u * 256 + threadIdx.x;
+        raw[u] = i < n ? J.src[sample_index(J.seed, t0 + i, J.n)] : 0;
+    }
+    uint32_t neg = 0, pos = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t i = u * 256 + threadIdx.x;
+        if (i < (1u << logN)) {
+            const uint64_t w = i < n ? to_ord(raw[u], J.dtype) : ~0ull;
+            s[base_pad(i)] = w;
+            if (i < n && J.dtype == kF64) {
+                neg += w <= kOrdNegInf;
+                pos += w >= kOrdPosInf;
+            }
+        }
+    }
+    if (neg)
+        atomicAdd(&s_nf[0], neg);
+    if (pos)
+        atomicAdd(&s_nf[1], pos);
     __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_nf[0])
+            atomicAdd((unsigned long long*)&nf[2 * j], (unsigned long long)s_nf[0]);
+        if (s_nf[1])
+            atomicAdd((unsigned long long*)&nf[2 * j + 1], (unsigned long long)s_nf[1]);
+    }
     lds_bitonic<256>(s, logN);
+    uint64_t* run = sample + J.sample_off + t0;
     for (uint32_t i = threadIdx.x; i < n; i += 256)
         run[i] = s[base_pad(i)];
 }
@@ -207,7 +198,8 @@ __global__ __launch_bounds__(256) void k_train_merge(const ModelJob* jobs, uint3
 // and each lane walks 16 consecutive ones; only a run that reaches past the
 // lane's range is searched for in global memory.
 __global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint32_t njobs, const uint64_t* sorted,
-                                                     uint64_t* best, uint64_t* firstc, const LiveCounts* live)
+                                                     uint64_t* best, uint64_t* firstc, const uint64_t* nf,
+                                                     const LiveCounts* live)
 {
     if (live) {
         if (blockIdx.x >= live->blocks)
@@ -221,9 +213,8 @@ __global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint3
     __shared__ uint64_t s_lo, s_hi;
     if (threadIdx.x == 0) {
         s_job = find_job(jobs, njobs, blockIdx.x);
-        const ModelJob J0 = jobs[s_job];
         uint64_t lo, hi;
-        finite_range(sorted + J0.sample_off, J0.m, J0.dtype, lo, hi);
+        finite_range(nf + 2 * s_job, jobs[s_job].m, lo, hi);
         s_lo = lo;
         s_hi = hi;
     }
@@ -257,8 +248,16 @@ __global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint3
             ++e;
         if (!(s_val[i] == x)) {                        // a run starts here (NaN before lo)
             uint64_t end = a + e;
-            if (e == r1)
-                end = value_upper(S, a + r1, hi, x, J.dtype);
+            if (e == r1) {
+                // the run reaches the lane's end: search the rest of the
+                // block in LDS, and past the block in global memory
+                uint32_t l = r1, h = nv;
+                while (l < h) {
+                    const uint32_t mid = (l + h) >> 1;
+                    if (s_val[mid + 1] > x) h = mid; else l = mid + 1;
+                }
+                end = l < nv ? a + l : value_upper(S, a + nv, hi, x, J.dtype);
+            }
             const uint32_t k = root_leaf(x, R, L);
             const uint64_t rel = a + i - lo, len = end - (a + i);
             atomicMax(&s_best[k], (unsigned long long)((len << 32) | (0xffffffffull - rel)));
@@ -277,7 +276,8 @@ __global__ __launch_bounds__(256) void k_train_modes(const ModelJob* jobs, uint3
 
 // Knots and segments of one job's model (one block per job).
 __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const uint64_t* sorted, uint64_t* best,
-                                                   uint64_t* firstc, double* models, const LiveCounts* live)
+                                                   uint64_t* firstc, uint64_t* nf, double* models,
+                                                   const LiveCounts* live)
 {
     if (live && blockIdx.x >= live->njobs)
         return;
@@ -291,10 +291,11 @@ __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const u
     const uint64_t* S = sorted + J.sample_off;
     if (threadIdx.x == 0) {
         uint64_t lo, hi;
-        finite_range(S, J.m, J.dtype, lo, hi);
+        finite_range(nf + 2 * blockIdx.x, J.m, lo, hi);
         s_lo = lo;
         s_hi = hi;
-        s_run0 = hi > lo ? value_upper(S, lo + 1, hi, ord_value(S[lo], J.dtype), J.dtype) - lo : 0;
+        // the run of the smallest finite value is leaf 0's first run
+        s_run0 = hi > lo ? (firstc[J.leaf_off] & 0xffffffffull) : 0;
     }
     const uint64_t* bt = best + J.leaf_off;
     for (uint32_t k = threadIdx.x; k < L; k += blockDim.x) {
@@ -401,16 +402,21 @@ __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const u
         best[J.leaf_off + k] = 0;
         firstc[J.leaf_off + k] = 0;
     }
+    if (threadIdx.x == 0) {
+        nf[2 * blockIdx.x] = 0;
+        nf[2 * blockIdx.x + 1] = 0;
+    }
 }
 
 hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_blocks, uint64_t total,
                         uint64_t max_sample, uint64_t* d_sample, uint64_t* d_tmp, uint64_t* d_best,
-                        uint64_t* d_first, double* d_models, const LiveCounts* live, hipStream_t st)
+                        uint64_t* d_first, uint64_t* d_nf, double* d_models, const LiveCounts* live,
+                        hipStream_t st)
 {
     if (!njobs || !total_blocks || !total)
         return hipSuccess;
-    k_train_sample<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, d_sample, live);
-    k_train_sort_runs<<<total_blocks, 256, (size_t)base_pad(kSampleBlock) * 8, st>>>(d_jobs, njobs, d_sample, live);
+    k_train_runs<<<total_blocks, 256, (size_t)base_pad(kSampleBlock) * 8, st>>>(d_jobs, njobs, d_sample, d_nf,
+                                                                                 live);
     uint64_t* src = d_sample;
     uint64_t* dst = d_tmp;
     for (uint64_t w = kSampleBlock; w < max_sample; w *= 2) {
@@ -419,8 +425,8 @@ hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_b
         src = dst;
         dst = t;
     }
-    k_train_modes<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, src, d_best, d_first, live);
-    k_train_fit<<<njobs, 256, 0, st>>>(d_jobs, src, d_best, d_first, d_models, live);
+    k_train_modes<<<total_blocks, 256, 0, st>>>(d_jobs, njobs, src, d_best, d_first, d_nf, live);
+    k_train_fit<<<njobs, 256, 0, st>>>(d_jobs, src, d_best, d_first, d_nf, d_models, live);
     return hipGetLastError();
 }
 
