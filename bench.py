@@ -407,8 +407,8 @@ def main():
     ap.add_argument("--segments", type=int, default=10_000, help="arrays of the segments workload")
     ap.add_argument("--requests", type=int, default=400, help="requests of the served workload")
     ap.add_argument("--budget-gb", type=int, default=200)
-    ap.add_argument("--inflight", type=int, default=2)
-    ap.add_argument("--graph", choices=("on", "off"), default="on",
+    ap.add_argument("--inflight", type=int, default=1, help="served workload: batches in flight at once")
+    ap.add_argument("--graph", choices=("on", "off"), default="off",
                     help="served workload: run requests and batches of up to 2^22 keys as graph replays")
     args = ap.parse_args()
     if args.summarize_trace:

@@ -201,8 +201,7 @@ typedef struct ls_server ls_server;
  * they need (keys already resident + the library's scratch) stays within
  * hbm_budget_bytes, batches the admitted ones into segmented sorts, and
  * keeps up to max_inflight batches in flight on separate streams.  p may be
- * NULL: the defaults with LS_FLAG_GRAPH (batches of up to 2^22 keys run as
- * graph replays). */
+ * NULL (the defaults; batches run host-driven unless p sets LS_FLAG_GRAPH). */
 ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
                            uint32_t max_inflight, const ls_params* p);
 

@@ -654,13 +654,14 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
     return LS_OK;
 }
 
-// The base case over the three size classes and the fills: classes 1 and
-// 2 on side streams forked from st and joined back, class 0 and the fills on
-// st (under capture, parallel branches of the graph).
+// The base case over the three size classes and the fills.  Host-driven:
+// classes 1 and 2 on side streams forked from st and joined back, class 0
+// and the fills on st.  Graph mode (gctl): all on st, so that no event or
+// side stream of the context takes part in a capture.
 ls_status launch_finish_lists(ls_ctx* C, const GroupLists& gl, const uint32_t* ngroups, const Fill* fills,
                               uint32_t nfill, const RoundCtl* gctl, hipStream_t st)
 {
-    const bool fork = gctl || (ngroups[1] && ngroups[2]) || ((ngroups[1] || ngroups[2]) && (ngroups[0] || nfill));
+    const bool fork = !gctl && ((ngroups[1] && ngroups[2]) || ((ngroups[1] || ngroups[2]) && (ngroups[0] || nfill)));
     if (!fork) {
         for (uint32_t c = 0; c < kGroupClasses; ++c)
             HIPCHECK(C, launch_base(gl.g[c], ngroups[c], c, gctl, st));

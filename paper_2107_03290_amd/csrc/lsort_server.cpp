@@ -4,10 +4,13 @@
 // `max_inflight` workers owns a library context and a HIP stream; when free
 // it admits queued requests in arrival order while the bytes they occupy on
 // the device (keys + the scratch the sort needs) stay within the budget, and
-// sorts them as one batch.  Requests that arrive while other batches run are
-// picked up by the next free worker, so batches overlap on the GPU.  The
-// admission stops at the first request that does not fit, so no request is
-// overtaken indefinitely.
+// sorts them as one batch.  A batch's keys are capped relative to its oldest
+// request, so a small request does not wait for a large one batched with it;
+// a request over the cap stays queued for a later batch.  Requests that
+// arrive while other batches run are picked up by the next free worker, so
+// batches overlap on the GPU.  The admission stops at the first request the
+// budget cannot hold, and a request is only passed by later arrivals until it
+// is the oldest, so none is overtaken indefinitely.
 #include "lsort.h"
 
 #include <hip/hip_runtime.h>
@@ -41,7 +44,17 @@ struct Done {
 };
 
 constexpr uint64_t kBytesPerKey = 16;             // the keys plus their scratch
-constexpr uint64_t kMaxBatchKeys = 1ull << 29;    // keeps batches short enough to interleave
+// A batch holds at most min(limit, max(kBatchFloorKeys, kBatchGrowth x its
+// first request's keys)) keys, or its first request alone: batching pays for
+// many small (launch-bound) requests, while a small request batched with a
+// large one waits for the large one.  The limit is kLatencyBatchKeys, or
+// kBacklogBatchKeys while more than kBacklog requests wait (then large
+// batches keep the device full and raise throughput).
+constexpr uint64_t kLatencyBatchKeys = 1ull << 25;
+constexpr uint64_t kBacklogBatchKeys = 1ull << 29;
+constexpr size_t kBacklog = 8;
+constexpr uint64_t kBatchFloorKeys = 1ull << 22;
+constexpr uint64_t kBatchGrowth = 4;
 
 }  // namespace
 
@@ -87,19 +100,34 @@ void worker_main(ls_server* S)
             });
             if (S->queue.empty())
                 break;
+            // The oldest request leads; later ones join while they fit the
+            // batch's key cap, and admission stops at the first request the
+            // memory budget cannot hold.  A request skipped for the cap is
+            // only ever passed by later arrivals until it leads a batch.
+            const uint64_t limit = S->queue.size() > kBacklog ? kBacklogBatchKeys : kLatencyBatchKeys;
+            const uint64_t cap = std::min(limit, std::max(kBatchFloorKeys, kBatchGrowth * S->queue.front().n));
+            // (the first request is admitted whatever its size)
             uint64_t keys = 0;
+            std::deque<Request> rest;
             while (!S->queue.empty()) {
-                const Request& r = S->queue.front();
-                uint64_t b = r.n * kBytesPerKey;
+                Request r = S->queue.front();
+                const uint64_t b = r.n * kBytesPerKey;
                 if (S->admitted + b > S->budget)
                     break;
-                if (!batch.empty() && keys + r.n > kMaxBatchKeys)
-                    break;
+                S->queue.pop_front();
+                if (!batch.empty() && keys + r.n > cap) {
+                    rest.push_back(r);
+                    continue;
+                }
                 S->admitted += b;
                 bytes += b;
                 keys += r.n;
                 batch.push_back(r);
-                S->queue.pop_front();
+            }
+            // skipped requests go back in front, in their order
+            while (!rest.empty()) {
+                S->queue.push_front(rest.back());
+                rest.pop_back();
             }
             S->peak = S->admitted > S->peak ? S->admitted : S->peak;
             S->n_batches++;
@@ -168,13 +196,10 @@ ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
         return LS_ERR_NOMEM;
     S->device = device;
     S->budget = hbm_budget_bytes;
-    if (p) {
+    if (p)
         S->params = *p;
-    } else {
-        // batches small enough run as graph replays by default
+    else
         ls_default_params(&S->params);
-        S->params.flags |= LS_FLAG_GRAPH;
-    }
     for (uint32_t i = 0; i < max_inflight; ++i)
         S->workers.emplace_back(worker_main, S);
     *out = S;
