@@ -71,6 +71,22 @@ def cpu_baseline(a: np.ndarray, sample: int):
                       % (sample, dt)}
 
 
+def cpu_library_sort(a: np.ndarray, sample: int):
+    """numpy's introsort (one thread) on the order-preserving words of the
+    same sample: a comparison-sort reference beside the oracle."""
+    w = np.ascontiguousarray(a[:sample]).view(np.uint64)
+    if a.dtype == np.float64:
+        sign = np.uint64(1 << 63)
+        w = np.where(w & sign, ~w, w | sign)
+    else:
+        w = w.copy()
+    t0 = time.perf_counter()
+    w.sort(kind="quicksort")
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "keys/s", "cores": 1, "kind": "numpy introsort on order words",
+            "sample": "first %d keys, %.1f s" % (sample, dt)}
+
+
 def roofline(prof: dict, wname: str) -> dict:
     """Roofline entry of the dominant kernel class: algorithmic bytes per
     launch over the average launch time (HIP events on the sort's stream)."""
@@ -291,7 +307,8 @@ def bench_served(args, torch, ls):
     S.close()
 
 
-KERNEL_CLASS_OF = (("k_train", "train"), ("k_hist", "hist"), ("k_scan", "scan"), ("k_classify", "classify"),
+KERNEL_CLASS_OF = (("k_upload", "upload"), ("k_train", "train"), ("k_hist", "hist"), ("k_scan", "scan"),
+                   ("k_classify", "classify"),
                    ("k_layout", "classify"), ("k_round_init", "classify"), ("k_scatter", "scatter"),
                    ("k_base", "base"), ("k_fill", "fill"), ("k_touchup", "touchup"))
 
@@ -503,6 +520,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(keys, min(args.cpu_sample, n))
+        line["cpu_library_sort"] = cpu_library_sort(keys, min(args.cpu_sample, n))
     print(json.dumps(line), flush=True)
     S.close()
 
