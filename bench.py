@@ -434,8 +434,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the sort runs on a single MI355X and this build has no "
-              "multi-GPU path (see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the sort runs on a single MI355X; there is no multi-GPU path "
+              "(sharding would sample per GPU, all-reduce the level-0 histogram and exchange keys once)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
