@@ -593,13 +593,13 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         // max(T/8, 2) keys (plus one piece per kFillPiece keys); a group of
         // class c > 0 holds more than the previous class cap; a group of
         // class 0 is a solo bucket (more than T keys) or starts where a run
-        // of small buckets is broken by the task start, a T-key window
-        // boundary or a big / fill / solo bucket, so there are at most
-        // 3 n/T + n/fill_min + 2 of them per task.
+        // of small buckets is broken by the task start, a W-key window
+        // boundary (W = group_window(T) <= T) or a big / fill / solo bucket,
+        // so there are at most 3 n/W + n/fill_min + 2 of them per task.
         const uint64_t max_tasks = std::min<uint64_t>(R.buckets, R.nkeys / (2ull * P.base)) + 1;
         const uint64_t fill_min = std::max<uint64_t>(P.base / 8, 2);
         const uint64_t max_fills = std::min<uint64_t>(R.buckets, R.nkeys / fill_min) + R.nkeys / kFillPiece + 1;
-        const uint64_t g0 = 3 * (R.nkeys / P.base) + R.nkeys / fill_min + 2 * (uint64_t)nt + 2;
+        const uint64_t g0 = 3 * (R.nkeys / group_window(P.base)) + R.nkeys / fill_min + 2 * (uint64_t)nt + 2;
         const uint64_t max_groups[kGroupClasses] = {std::min<uint64_t>(R.buckets, g0) + 1,
                                                     R.nkeys / (kGroupClassCap[0] + 1) + 1,
                                                     R.nkeys / (kGroupClassCap[1] + 1) + 1};
@@ -824,7 +824,8 @@ Caps graph_caps(uint64_t keys, uint64_t arrays, const Params& P)
     // lists: the per-round bounds of rounds_eager, over every round, plus
     // the small arrays of round 0
     const uint64_t fill_min = std::max<uint64_t>(P.base / 8, 2);
-    const uint64_t g0 = std::min<uint64_t>(K.buckets, 3 * (N / T) + N / fill_min + 2 * K.tasks + 2) + 1;
+    const uint64_t g0 =
+        std::min<uint64_t>(K.buckets, 3 * (N / group_window(P.base)) + N / fill_min + 2 * K.tasks + 2) + 1;
     K.groups[0] = arrays + kGraphMaxRounds * g0;
     K.groups[1] = arrays + kGraphMaxRounds * (N / (kGroupClassCap[0] + 1) + 1);
     K.groups[2] = arrays + kGraphMaxRounds * (N / (kGroupClassCap[1] + 1) + 1);

@@ -180,6 +180,14 @@ __host__ __device__ inline size_t scatter_lds_bytes(uint32_t tile, uint32_t fano
     return ((size_t)tile * 10 + (size_t)fanout * 16 + 15) & ~(size_t)15;
 }
 
+// Keys per window within which consecutive small buckets are sorted as one
+// base-case group.
+constexpr uint32_t kGroupWindow = 512;
+__host__ __device__ inline uint32_t group_window(uint32_t thresh)
+{
+    return thresh < kGroupWindow ? thresh : kGroupWindow;
+}
+
 __host__ __device__ inline uint32_t pow2_at_least(uint64_t x)
 {
     uint32_t p = 1;

@@ -263,8 +263,11 @@ hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chun
 // solo (more than `thresh` but fewer than 2*thresh keys: sorted in LDS as a
 // group of its own) or over-full (a task of the next round).  Small buckets
 // hold at most `thresh` keys; consecutive small buckets whose starts fall into
-// the same window of `thresh` keys form one group, so a group holds fewer than
-// 2*thresh keys.  Everything is decided with block-wide scans, no serial walk.
+// the same window of group_window(thresh) keys form one group, so a group
+// holds fewer than 2*thresh keys.  The buckets of a group are already in
+// order, so a small window keeps the LDS sorts short (the base case's
+// network grows as log^2 of the group).  Everything is decided with
+// block-wide scans, no serial walk.
 enum : uint8_t { kEmpty = 0, kSmall = 1, kFillB = 2, kBig = 3, kSolo = 4, kLead = 0x80 };
 
 constexpr int32_t kNone = 0x7fffffff;
@@ -519,6 +522,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
         bst[f] = T.n;
     }
     const uint32_t fill_min = thresh / 8u > 2u ? thresh / 8u : 2u;
+    const uint32_t gw = group_window(thresh);
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
         const uint64_t s0 = pos[T.cnt_off + (uint64_t)b * T.nchunks] - T.cnt_base;
         const uint64_t s1 = (b + 1 < f) ? pos[T.cnt_off + (uint64_t)(b + 1) * T.nchunks] - T.cnt_base : T.n;
@@ -550,7 +554,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
         bool lead = k == kSolo;
         if (k == kSmall) {
             const int32_t p = prv[b];
-            lead = p < 0 || kind[p] != kSmall || bst[p] / thresh != bst[b] / thresh;
+            lead = p < 0 || kind[p] != kSmall || bst[p] / gw != bst[b] / gw;
         }
         const bool brk = k != kEmpty && (lead || k != kSmall);
         nxt[f - 1 - b] = brk ? (int32_t)b : kNone;
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
         const int32_t p = prv[b];
         const uint8_t k = kind[b];
         const bool lead = k == kSolo ||
-                          (k == kSmall && (p < 0 || kind[p] != kSmall || bst[p] / thresh != bst[b] / thresh));
+                          (k == kSmall && (p < 0 || kind[p] != kSmall || bst[p] / gw != bst[b] / gw));
         prv[b] = lead ? 1 : 0;     // temporary: leader flag
     }
     __syncthreads();
