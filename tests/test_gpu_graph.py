@@ -172,3 +172,27 @@ def test_graph_touchup_repair(S):
     check(a, got, off)
     assert st["seams_repaired"] > 0
     assert S.sync() & ls.DEV_SEAM_REPAIRED
+
+
+def test_graph_flag_combinations_and_classes(S):
+    # profiling and the full touch-up check run host-driven; a batch above
+    # 2^22 keys runs host-driven; 100 arrays use the 128-array class
+    keys, off = batch(40, 77)
+    for flags in (0x10 | ls.FLAG_PROFILE, 0x10 | ls.FLAG_DEBUG_TOUCHUP):
+        print("graph flags=%#x" % flags, flush=True)
+        S.profile_reset()
+        got, st = sort_batch(S, keys, off, ls.params(flags=flags))
+        check(keys, got, off)
+        assert st["seams_repaired"] == 0
+        if flags & ls.FLAG_PROFILE:
+            assert S.profile()["scatter"][1] > 0
+    big, off_big = batch(30, 78, lo=100_000, hi=400_000)
+    assert int(off_big[-1]) > (1 << 22)
+    print("graph large batch keys=%d" % big.size, flush=True)
+    got, _ = sort_batch(S, big, off_big, ls.params(**GRAPH))
+    check(big, got, off_big)
+    many, off_many = batch(100, 79, hi=60_000)
+    for rep in range(2):
+        print("graph 100 arrays rep=%d" % rep, flush=True)
+        got, _ = sort_batch(S, many, off_many, ls.params(**GRAPH))
+        check(many, got, off_many)
