@@ -511,7 +511,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if keys.dtype == np.float64 else "u64",
         "data": "synthetic (seeded generator; no dataset)",
-        "config": {"workload": wname, "n": n, "fanout": p.fanout, "leaves": p.leaves, "tile": p.tile,
+        "config": {"workload": wname, "n": n, "fanout": p.fanout, "leaves": p.leaves,
+                   "tile": p.tile or "auto (4096; 8192 in rounds of >= 2^25 keys)",
                    "base_threshold": p.base_threshold, "sample_rate": p.sample_rate, "sample_cap": p.sample_cap},
         "roofline": roofline(prof, wname),
         "kernel_ms_per_step": {k: prof[k][0] / K for k in prof},

@@ -68,7 +68,9 @@ typedef struct {
     uint32_t struct_size;      /* sizeof(ls_params) */
     uint32_t fanout;           /* f: buckets per partition, 2..4096 (default 1024) */
     uint32_t leaves;           /* L: leaf models of the two-layer model, 1..1024 (default 1024) */
-    uint32_t tile;             /* keys staged per partition tile in LDS 1024, 2048 or 4096 (default 4096) */
+    uint32_t tile;             /* keys staged per scatter tile in LDS: 1024, 2048, 4096 or 8192, or 0
+                                  (ls_default_params) for automatic: 4096, and 8192 in host-driven rounds
+                                  of at least 2^25 keys whose fanouts leave room for it in LDS */
     uint32_t base_threshold;   /* buckets of at most this many keys are sorted in LDS, in groups of < 2x (default 4096, max 4096) */
     uint32_t flags;            /* LS_FLAG_* */
     double   sample_rate;      /* model training sample (default 0.01) */

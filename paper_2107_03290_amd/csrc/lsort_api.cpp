@@ -45,6 +45,8 @@ struct PinBuf {
 
 struct Params {
     uint32_t fanout, leaves, tile, base, flags;
+    uint32_t tile_wide = 0;         // automatic tile: large rounds use this one (0: never)
+    uint32_t wide_max_fanout = 0;   // largest task fanout whose wide-tile scatter fits in LDS
     double rate;
     uint64_t cap, seed;
 };
@@ -329,6 +331,7 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
     P.fanout = kDefaultFanout;
     P.leaves = kDefaultLeaves;
     P.tile = kDefaultTile;
+    P.tile_wide = p ? 0 : 2 * kDefaultTile;
     P.base = kDefaultBase;
     P.flags = 0;
     P.rate = 0.01;
@@ -340,6 +343,7 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
         if (p->fanout) P.fanout = p->fanout;
         if (p->leaves) P.leaves = p->leaves;
         if (p->tile) P.tile = p->tile;
+        else P.tile_wide = 2 * kDefaultTile;
         if (p->base_threshold) P.base = p->base_threshold;
         P.flags = p->flags;
         if (p->sample_rate != 0.0) P.rate = p->sample_rate;
@@ -350,8 +354,8 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
         return fail(C, LS_ERR_INVALID, "fanout must be in [2, 4096]");
     if (P.leaves < 1 || P.leaves > kMaxLeaves)
         return fail(C, LS_ERR_INVALID, "leaves must be in [1, 1024]");
-    if (P.tile != 1024 && P.tile != 2048 && P.tile != 4096)
-        return fail(C, LS_ERR_INVALID, "tile must be 1024, 2048 or 4096");
+    if (P.tile != 1024 && P.tile != 2048 && P.tile != 4096 && P.tile != 8192)
+        return fail(C, LS_ERR_INVALID, "tile must be 0 (automatic), 1024, 2048, 4096 or 8192");
     if (P.base < 2 || 2 * P.base > kMaxBase)
         return fail(C, LS_ERR_INVALID, "base_threshold must be in [2, 4096]");
     if (!(P.rate > 0.0) || P.rate > 1.0)
@@ -360,6 +364,15 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
     size_t hist_lds = (((size_t)P.fanout * 20 + 15) & ~(size_t)15) + model_lds_bytes(P.leaves) + 64;
     if (scatter_lds > C->lds_limit || hist_lds > C->lds_limit)
         return fail(C, LS_ERR_UNSUPPORTED, "tile/fanout/leaves exceed the LDS of one workgroup");
+    // automatic tile: the wide tile is taken only by rounds whose fanouts fit
+    P.wide_max_fanout = 0;
+    if (P.tile_wide) {
+        const size_t fixed = scatter_lds_bytes(P.tile_wide, 0) + 128 + 16;
+        P.wide_max_fanout = C->lds_limit > fixed ? (uint32_t)std::min<size_t>((C->lds_limit - fixed) / 24, kMaxFanout)
+                                                 : 0u;
+        if (P.wide_max_fanout < 2)
+            P.tile_wide = 0;
+    }
     return LS_OK;
 }
 
@@ -554,6 +567,9 @@ LayoutParams layout_params(const Params& P, uint64_t model_base)
     lp.fanout = P.fanout;
     lp.leaves = P.leaves;
     lp.tile = P.tile;
+    lp.tile_wide = P.tile_wide;
+    lp.wide_keys = kWideTileKeys;
+    lp.wide_max_fanout = P.wide_max_fanout;
     lp.rate = P.rate;
     lp.cap = P.cap;
     lp.seed = P.seed;
@@ -638,7 +654,7 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         prof.begin(4);
         HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const uint16_t*)C->ids.p,
                                    (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
-                                   (const uint32_t*)C->tflags.p, P.tile, R.max_fanout, nullptr, st));
+                                   (const uint32_t*)C->tflags.p, R.tile, R.max_fanout, nullptr, st));
         prof.end(0.0);
         TRY(wait_ctl(C, st));
         if (prof.on && !prof.recs.empty()) {
@@ -879,6 +895,7 @@ ls_status size_for_graph(ls_ctx* C, const Caps& K, hipStream_t st)
 LayoutParams graph_layout_params(ls_ctx* C, const Caps& K, const Params& P)
 {
     LayoutParams lp = layout_params(P, K.gmodels);
+    lp.tile_wide = 0;   // the captured scatter launch has one tile
     lp.cap_tasks = K.tasks;
     lp.cap_fills = C->fills.cap / sizeof(Fill);
     for (uint32_t c = 0; c < kGroupClasses; ++c)
@@ -1129,7 +1146,7 @@ void ls_default_params(ls_params* p)
     p->struct_size = sizeof(ls_params);
     p->fanout = kDefaultFanout;
     p->leaves = kDefaultLeaves;
-    p->tile = kDefaultTile;
+    p->tile = 0;   // automatic
     p->base_threshold = kDefaultBase;
     p->sample_rate = 0.01;
     p->seed = kDefaultSeed;

@@ -12,6 +12,24 @@
 
 namespace lsort {
 
+// ------------------------------------------------------- global pointers --
+
+// Key and range pointers are read from descriptors in memory, so the compiler
+// cannot tell which address space they point into and accesses through them
+// become flat instructions.  On gfx9 a flat access also counts against the
+// LDS wait counter: every wait for an LDS result would then also wait for the
+// keys in flight (the next tile's prefetch) and for earlier stores.  Every
+// buffer the library hands to a kernel is device (global) memory, so such
+// pointers are cast to the global address space before use.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T* p)
+{
+    return (gptr<T>)p;
+}
+
 constexpr uint64_t kSign = 0x8000000000000000ull;
 constexpr uint64_t kSkipBit = 0x8000000000000000ull;
 constexpr uint32_t kNoScatter = 1u;

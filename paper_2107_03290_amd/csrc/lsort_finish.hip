@@ -26,6 +26,8 @@ __global__ __launch_bounds__(NT) void k_base(const Group* groups, uint32_t ngrou
     // one group per workgroup; a grid smaller than the list strides over it
     for (uint32_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const Group G = groups[g];
+        const gptr<const uint64_t> src = as_global(G.src);
+        const gptr<uint64_t> dst = as_global(G.dst);
         const uint32_t n = G.n;
         if (n > NT * 16u)        // never produced by classify; keeps LDS in bounds
             continue;
@@ -34,11 +36,11 @@ __global__ __launch_bounds__(NT) void k_base(const Group* groups, uint32_t ngrou
             ++logN;
         const uint32_t N = 1u << logN;
         for (uint32_t i = threadIdx.x; i < N; i += NT)
-            s[base_pad(i)] = i < n ? to_ord(G.src[i], G.dtype) : ~0ull;
+            s[base_pad(i)] = i < n ? to_ord(src[i], G.dtype) : ~0ull;
         __syncthreads();
         lds_bitonic<NT>(s, logN);
         for (uint32_t i = threadIdx.x; i < n; i += NT)
-            G.dst[i] = from_ord(s[base_pad(i)], G.dtype);
+            dst[i] = from_ord(s[base_pad(i)], G.dtype);
         __syncthreads();
     }
 }
@@ -75,8 +77,9 @@ __global__ __launch_bounds__(256) void k_fill(const Fill* fills, uint32_t nfill,
     }
     for (uint32_t f = blockIdx.x; f < nfill; f += gridDim.x) {
         const Fill F = fills[f];
+        const gptr<uint64_t> dst = as_global(F.dst);
         for (uint32_t i = threadIdx.x; i < F.n; i += 256)
-            F.dst[i] = F.raw;
+            dst[i] = F.raw;
     }
 }
 
@@ -120,19 +123,22 @@ __global__ __launch_bounds__(256) void k_touchup(RangeLists R, RoundCtl* ctl, bo
         uint32_t dt = 0;
         for (uint32_t c = 0; c < kGroupClasses && !p; ++c) {
             if (i < R.ng[c]) {
-                p = R.g[c][i].dst;
-                start = R.g[c][i].start;
-                dt = R.g[c][i].dtype;
+                const gptr<const Group> g = as_global(R.g[c]);
+                p = g[i].dst;
+                start = g[i].start;
+                dt = g[i].dtype;
             } else {
                 i -= R.ng[c];
             }
         }
         if (!p) {
-            p = R.fills[i].dst;
-            start = R.fills[i].start;
-            dt = R.fills[i].dtype;
+            const gptr<const Fill> fl = as_global(R.fills);
+            p = fl[i].dst;
+            start = fl[i].start;
+            dt = fl[i].dtype;
         }
-        bad += start > 0 && to_ord(p[-1], dt) > to_ord(p[0], dt);
+        const gptr<const uint64_t> q = as_global(p);
+        bad += start > 0 && to_ord(q[-1], dt) > to_ord(q[0], dt);
     }
     if (bad)
         atomicAdd(&ctl->violations, bad);
@@ -141,9 +147,10 @@ __global__ __launch_bounds__(256) void k_touchup(RangeLists R, RoundCtl* ctl, bo
 __global__ __launch_bounds__(256) void k_touchup_full(const Group* groups, RoundCtl* ctl)
 {
     const Group G = groups[blockIdx.x];
+    const gptr<const uint64_t> d = as_global<const uint64_t>(G.dst);
     uint32_t bad = 0;
     for (uint32_t i = threadIdx.x + 1; i < G.n; i += 256)
-        bad += to_ord(G.dst[i - 1], G.dtype) > to_ord(G.dst[i], G.dtype);
+        bad += to_ord(d[i - 1], G.dtype) > to_ord(d[i], G.dtype);
     if (bad)
         atomicAdd(&ctl->violations, bad);
 }

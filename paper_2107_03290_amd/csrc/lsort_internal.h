@@ -96,7 +96,10 @@ struct ModelJob {
 struct LayoutParams {
     uint32_t fanout;      // the caller's fanout
     uint32_t leaves;
-    uint32_t tile;
+    uint32_t tile;        // keys per scatter tile
+    uint32_t tile_wide;   // tile of rounds of at least wide_keys keys (0: always `tile`)
+    uint64_t wide_keys;
+    uint32_t wide_max_fanout;   // largest task fanout whose wide-tile scatter fits in LDS
     uint32_t pad;
     double rate;
     uint64_t cap;
@@ -145,6 +148,8 @@ struct RoundCtl {
     // written by the layout kernel, cumulative over the sort
     uint32_t rounds;                  // rounds laid out with at least one task
     uint32_t deepest;                 // largest task level laid out
+    uint32_t tile;                    // scatter tile of the next round (written by the layout)
+    uint32_t pad;
     uint64_t tasks_total;             // tasks over all rounds
     LiveCounts cur;                   // graph mode: the running round's sizes
 };
@@ -173,11 +178,17 @@ __host__ __device__ inline size_t model_lds_bytes(uint32_t L)
     return (size_t)(L + 1) * 40 + (size_t)L * 2 + 32;
 }
 
+// Keys of a round from which the default tile is doubled: a larger tile
+// makes longer runs per bucket in the scatter's writes, and a round this
+// large still has thousands of chunks.
+constexpr uint64_t kWideTileKeys = 1ull << 25;
+
 // LDS bytes of the scatter: the staged tile (8 B keys + 2 B ids) and, per
-// bucket, the cursor (8 B), tile count and tile start (4 B each).
+// bucket, the cursor and the tile's write base (8 B each), tile count and
+// tile start (4 B each).
 __host__ __device__ inline size_t scatter_lds_bytes(uint32_t tile, uint32_t fanout)
 {
-    return ((size_t)tile * 10 + (size_t)fanout * 16 + 15) & ~(size_t)15;
+    return ((size_t)tile * 10 + (size_t)fanout * 24 + 15) & ~(size_t)15;
 }
 
 // Keys per window within which consecutive small buckets are sorted as one

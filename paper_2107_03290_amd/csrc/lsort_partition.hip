@@ -141,7 +141,7 @@ __device__ __forceinline__ void wave_count(uint32_t* h, uint32_t b, bool valid)
 }
 
 template <uint32_t DT, bool MSD>
-__device__ __forceinline__ void hist_body(const Task& T, const SModel& M, const uint64_t* src, uint32_t cnt,
+__device__ __forceinline__ void hist_body(const Task& T, const SModel& M, gptr<const uint64_t> src, uint32_t cnt,
                                           uint32_t* h, unsigned long long* mn, unsigned long long* mx,
                                           uint16_t* ids, uint32_t flags)
 {
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32
     const uint32_t lc = blockIdx.x - T.chunk0;
     const uint64_t lo = (uint64_t)lc * chunk;
     const uint32_t n = (uint32_t)(min(T.n, lo + chunk) - lo);
-    const uint64_t* src = (T.src ? T.scratch : T.keys) + T.start + lo;
+    const gptr<const uint64_t> src = as_global<const uint64_t>((T.src ? T.scratch : T.keys) + T.start + lo);
     uint16_t* cid = ids + T.cnt_base + lo;
     if (T.dtype == kF64) {
         if (msd) hist_body<kF64, true>(T, M, src, n, h, mn, mx, cid, flags);
@@ -322,13 +322,16 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
     }
     __syncthreads();
     const uint64_t nkeys = s_keys;
+    // a large round scatters in wide tiles when its fanouts leave room in LDS
+    const uint32_t tile =
+        lp.tile_wide && nkeys >= lp.wide_keys && s_maxf <= lp.wide_max_fanout ? lp.tile_wide : lp.tile;
     // at most kTargetChunks chunks; a small round gets about one chunk per
     // CU, of one to four tiles
     uint64_t chunk = (nkeys + kTargetChunks - 1) / kTargetChunks;
     uint64_t small = (nkeys + kSmallRoundChunks - 1) / kSmallRoundChunks;
-    small = small < lp.tile ? lp.tile : (small > 4ull * lp.tile ? 4ull * lp.tile : small);
+    small = small < tile ? tile : (small > 4ull * tile ? 4ull * tile : small);
     chunk = chunk > small ? chunk : small;
-    chunk = (chunk + lp.tile - 1) / lp.tile * lp.tile;
+    chunk = (chunk + tile - 1) / tile * tile;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     uint32_t my_maxl = 1;
     unsigned long long my_maxm = 0;
@@ -441,6 +444,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
                 carry[j] = 0;
         }
         ctl->chunk = chunk;
+        ctl->tile = tile;
         ctl->nkeys = over ? 0 : nkeys;
         ctl->chunks = (uint32_t)carry[0];
         ctl->buckets = carry[1];
@@ -747,22 +751,54 @@ constexpr uint32_t kScatterThreads = 1024;
 // ids come from the histogram pass (one u16 per key), so no model is
 // evaluated here.  The next tile's keys and ids are loaded while the current
 // one is ranked and written.
-template <uint32_t KPT>
-__device__ __forceinline__ void scatter_body(const Task& T, const uint64_t* src, const uint16_t* ids, uint64_t* dst,
-                                             uint32_t n, unsigned char* smem, uint32_t* wsum)
+//
+// LDS: the staged tile (8 B keys), then per bucket the cursor and the tile's
+// write base (8 B each), the tile count and tile start (4 B each), then the
+// staged ids (2 B per key).
+struct ScatterLds {
+    uint64_t* stage;
+    uint64_t* cur;
+    uint64_t* wbase;
+    uint32_t* tcnt;
+    uint32_t* tstart;
+    uint16_t* sb;
+};
+
+__device__ __forceinline__ ScatterLds scatter_lds(unsigned char* smem, uint32_t tile, uint32_t f)
 {
-    constexpr uint32_t TILE = KPT * kScatterThreads;
+    ScatterLds L;
+    L.stage = reinterpret_cast<uint64_t*>(smem);
+    L.cur = L.stage + tile;
+    L.wbase = L.cur + f;
+    L.tcnt = reinterpret_cast<uint32_t*>(L.wbase + f);
+    L.tstart = L.tcnt + f;
+    L.sb = reinterpret_cast<uint16_t*>(L.tstart + f);
+    return L;
+}
+
+// One tile takes five barriers: after ranking; two inside the scan of the
+// tile counts; after the scan (which also moves the cursors on and clears the
+// counts, so the write loop needs only the write base); after staging.  The
+// write loop needs none behind it: the next tile's ranking touches only the
+// counts and the cursors' skip bits, and everything the write loop reads is
+// rewritten only after the next tile's first barrier.
+template <uint32_t KPT>
+__device__ __forceinline__ void scatter_body(const Task& T, gptr<const uint64_t> src, const uint16_t* ids,
+                                             gptr<uint64_t> dst, uint32_t n, const ScatterLds& L,
+                                             uint32_t* wsum)
+{
+    constexpr uint32_t NT = kScatterThreads;
+    constexpr uint32_t TILE = KPT * NT;
     const uint32_t f = T.fanout;
-    uint64_t* stage = reinterpret_cast<uint64_t*>(smem);
-    uint64_t* cur = stage + TILE;
-    uint32_t* tcnt = reinterpret_cast<uint32_t*>(cur + f);
-    uint32_t* tstart = tcnt + f;
-    uint16_t* sb = reinterpret_cast<uint16_t*>(tstart + f);
+    // buckets of this thread in the tile scan
+    const uint32_t per = (f + NT - 1) / NT;
+    const uint32_t blo = min(f, threadIdx.x * per), bhi = min(f, blo + per);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     uint64_t nxt[KPT];
-    uint16_t nid[KPT];
+    uint32_t nid[KPT];   // widened: packing two ids per register would wait for the loads
 #pragma unroll
     for (uint32_t u = 0; u < KPT; ++u) {
-        const uint32_t i = u * kScatterThreads + threadIdx.x;
+        const uint32_t i = u * NT + threadIdx.x;
         nxt[u] = i < n ? src[i] : 0;
         nid[u] = i < n ? ids[i] : 0;
     }
@@ -770,7 +806,7 @@ __device__ __forceinline__ void scatter_body(const Task& T, const uint64_t* src,
         uint64_t raw[KPT];
         uint32_t bk[KPT];
         uint32_t rk[KPT];
-        uint16_t id[KPT];
+        uint32_t id[KPT];
 #pragma unroll
         for (uint32_t u = 0; u < KPT; ++u) {
             raw[u] = nxt[u];
@@ -779,45 +815,64 @@ __device__ __forceinline__ void scatter_body(const Task& T, const uint64_t* src,
         if (base + TILE < n) {
 #pragma unroll
             for (uint32_t u = 0; u < KPT; ++u) {
-                const uint32_t i = base + TILE + u * kScatterThreads + threadIdx.x;
+                const uint32_t i = base + TILE + u * NT + threadIdx.x;
                 nxt[u] = i < n ? src[i] : 0;
                 nid[u] = i < n ? ids[i] : 0;
             }
         }
+        // rank each key among the tile's keys of its bucket
 #pragma unroll
         for (uint32_t u = 0; u < KPT; ++u) {
-            const uint32_t i = base + u * kScatterThreads + threadIdx.x;
+            const uint32_t i = base + u * NT + threadIdx.x;
             bk[u] = ~0u;
             rk[u] = 0;
             if (i < n) {
                 const uint32_t b = id[u];
-                if (!(cur[b] & kSkipBit)) {
+                if (!(L.cur[b] & kSkipBit)) {
                     bk[u] = b;
-                    rk[u] = atomicAdd(&tcnt[b], 1u);
+                    rk[u] = atomicAdd(&L.tcnt[b], 1u);
                 }
             }
         }
         __syncthreads();
-        const uint32_t ntile = block_scan_u32(tcnt, tstart, f, wsum);
+        // exclusive scan of the tile counts; write base = cursor - tile start
+        uint32_t s = 0;
+        for (uint32_t b = blo; b < bhi; ++b)
+            s += L.tcnt[b];
+        uint32_t x = s;
+#pragma unroll
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d)
+                x += y;
+        }
+        if (lane == 63)
+            wsum[wave] = x;
+        __syncthreads();
+        wave_totals_scan<uint32_t>(wsum, NT / 64, 0u, AddU32());
+        __syncthreads();
+        uint32_t run = wsum[wave] + x - s;
+        for (uint32_t b = blo; b < bhi; ++b) {
+            const uint32_t c = L.tcnt[b];
+            L.tstart[b] = run;
+            L.wbase[b] = L.cur[b] - run;   // modulo 2^64; a bucket with no key here is never read
+            L.cur[b] += c;
+            L.tcnt[b] = 0;
+            run += c;
+        }
+        const uint32_t ntile = wsum[NT / 64];
+        __syncthreads();
 #pragma unroll
         for (uint32_t u = 0; u < KPT; ++u) {
             if (bk[u] != ~0u) {
-                const uint32_t p = tstart[bk[u]] + rk[u];
-                stage[p] = raw[u];
-                sb[p] = (uint16_t)bk[u];
+                const uint32_t p = L.tstart[bk[u]] + rk[u];
+                L.stage[p] = raw[u];
+                L.sb[p] = (uint16_t)bk[u];
             }
         }
         __syncthreads();
-        for (uint32_t p = threadIdx.x; p < ntile; p += kScatterThreads) {
-            const uint32_t b = sb[p];
-            dst[cur[b] + (p - tstart[b])] = stage[p];
-        }
-        __syncthreads();
-        for (uint32_t b = threadIdx.x; b < f; b += kScatterThreads) {
-            cur[b] += tcnt[b];
-            tcnt[b] = 0;
-        }
-        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < ntile; p += NT)
+            dst[L.wbase[L.sb[p]] + p] = L.stage[p];
     }
 }
 
@@ -845,20 +900,19 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, 
         return;
     const Task T = tasks[ti];
     const uint32_t f = T.fanout;
-    uint64_t* cur = reinterpret_cast<uint64_t*>(smem) + TILE;
-    uint32_t* tcnt = reinterpret_cast<uint32_t*>(cur + f);
+    const ScatterLds L = scatter_lds(smem, TILE, f);
     const uint32_t lc = blockIdx.x - T.chunk0;
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
         const uint64_t c = pos[T.cnt_off + (uint64_t)b * T.nchunks + lc] - T.cnt_base;
-        cur[b] = skip[(uint64_t)T.bucket_off + b] ? (c | kSkipBit) : c;
-        tcnt[b] = 0;
+        L.cur[b] = skip[(uint64_t)T.bucket_off + b] ? (c | kSkipBit) : c;
+        L.tcnt[b] = 0;
     }
     __syncthreads();
     const uint64_t lo = (uint64_t)lc * chunk;
     const uint32_t n = (uint32_t)(min(T.n, lo + chunk) - lo);
-    const uint64_t* src = (T.src ? T.scratch : T.keys) + T.start + lo;
-    uint64_t* dst = (T.src ? T.keys : T.scratch) + T.start;
-    scatter_body<KPT>(T, src, ids + T.cnt_base + lo, dst, n, smem, wsum);
+    const gptr<const uint64_t> src = as_global<const uint64_t>((T.src ? T.scratch : T.keys) + T.start + lo);
+    const gptr<uint64_t> dst = as_global((T.src ? T.keys : T.scratch) + T.start);
+    scatter_body<KPT>(T, src, ids + T.cnt_base + lo, dst, n, L, wsum);
 }
 
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
@@ -880,6 +934,10 @@ hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_c
         break;
     case 4096:
         k_scatter<4><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
+                                                                  d_task_flags, live);
+        break;
+    case 8192:
+        k_scatter<8><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
                                                                   d_task_flags, live);
         break;
     default:

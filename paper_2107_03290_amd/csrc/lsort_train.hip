@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_train_runs(const ModelJob* jobs, uint32
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
         const uint32_t i = u * 256 + threadIdx.x;
-        raw[u] = i < n ? J.src[sample_index(J.seed, t0 + i, J.n)] : 0;
+        raw[u] = i < n ? as_global<const uint64_t>(J.src)[sample_index(J.seed, t0 + i, J.n)] : 0;
     }
     uint32_t neg = 0, pos = 0;
 #pragma unroll
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(256) void k_train_small(const ModelJob* jobs, doubl
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
         const uint32_t i = u * 256 + threadIdx.x;
-        raw[u] = i < n ? J.src[sample_index(J.seed, i, J.n)] : 0;
+        raw[u] = i < n ? as_global<const uint64_t>(J.src)[sample_index(J.seed, i, J.n)] : 0;
     }
     __syncthreads();
     uint32_t neg = 0, pos = 0;

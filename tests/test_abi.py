@@ -42,7 +42,7 @@ def test_status_strings_host_only():
 def test_default_params_host_only():
     p = ls.params()
     assert p.struct_size == ctypes.sizeof(ls.Params) == 48
-    assert (p.fanout, p.leaves, p.tile, p.base_threshold) == (1024, 1024, 4096, 4096)
+    assert (p.fanout, p.leaves, p.tile, p.base_threshold) == (1024, 1024, 0, 4096)   # tile 0: automatic
     assert p.sample_rate == 0.01
     assert p.sample_cap == 1 << 18          # the 1% rate holds up to 26.2M keys
 

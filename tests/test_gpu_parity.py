@@ -142,7 +142,8 @@ def test_sort_matches_oracle(S, name, n):
 
 
 @pytest.mark.parametrize("kw", [dict(fanout=2), dict(fanout=16, leaves=8), dict(fanout=1000, leaves=1000),
-                                dict(fanout=4096, leaves=256, tile=4096), dict(tile=1024),
+                                dict(fanout=4096, leaves=256, tile=4096), dict(tile=1024), dict(tile=8192),
+                                dict(tile=8192, fanout=2048), dict(tile=4096),
                                 dict(base_threshold=2), dict(base_threshold=64, fanout=8),
                                 dict(base_threshold=4096, fanout=64), dict(sample_rate=0.5),
                                 dict(sample_cap=100), dict(leaves=1)])
@@ -151,6 +152,27 @@ def test_parameters_never_change_the_result(S, kw, name):
     a = inputs(name, 150_000, 23)
     got = gpu_sort(S, a, ls.params(**kw))
     assert np.array_equal(got, expected_sorted(a))
+
+
+def test_wide_tile_rounds_match_the_definition(S):
+    # the automatic tile scatters rounds of at least 2^25 keys in 8192-key
+    # tiles (the round-0 task here, and the over-full buckets after it);
+    # a fixed 4096-key tile must give the same words
+    a = W.zipf_lognormal((1 << 25) + 12_345, seed=14, distinct=400_000)
+    want = expected_sorted(a)
+    for kw in (dict(), dict(tile=4096)):
+        print("wide tile n=%d params=%s" % (a.size, kw), flush=True)
+        got = gpu_sort(S, a, ls.params(**kw))
+        assert np.array_equal(got, want)
+
+
+def test_tile_that_does_not_fit_is_rejected(S):
+    # 8192-key tiles with 4096 buckets need more LDS than one workgroup has
+    t = torch.zeros(10, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ls.LsortError):
+        S.sort_(t, ls.params(tile=8192, fanout=4096))
+    with pytest.raises(ls.LsortError):
+        S.sort_(t, ls.params(tile=3000))
 
 
 def test_debug_touchup_full_check(S):
