@@ -168,7 +168,8 @@ def bench_segments(args, torch, ls):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator; no dataset)",
         "config": {"workload": "segments_%d_f64" % (off.size - 1), "keys": n, "fanout": best.fanout,
-                   "tile": best.tile, "base_threshold": best.base_threshold, "autotune_s": t_tune},
+                   "tile": best.tile or "auto (4096; 8192 in rounds of >= 2^25 keys)",
+                   "base_threshold": best.base_threshold, "autotune_s": t_tune},
         "plain": {"value": n / (ms_p / 1e3), "unit": "keys/s", "ms": ms_p,
                   "calls": int(off.size - 1), "params": "defaults"},
         "batched_over_plain": ms_p / ms,

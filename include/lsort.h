@@ -143,7 +143,7 @@ typedef struct {
  * the caller's keys are NOT modified) once per candidate and repetition,
  * timed with HIP events on `stream`, and writes the fastest configuration to
  * *best (every other field copied from `base`, which may be NULL).  The
- * candidates are fanout in {512, 1024, 2048, 4096} x tile in {2048, 4096} x
+ * candidates are fanout in {512, 1024, 2048, 4096} x tile in {2048, 0 (automatic)} x
  * base_threshold in {1024, 2048, 4096}.  No candidate changes the sorted
  * result, so tuning only affects speed.  results (HOST, may be NULL) receives
  * up to cap entries and *n_results the number of candidates.  reps = 0 means

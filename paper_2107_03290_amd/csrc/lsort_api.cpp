@@ -1348,7 +1348,7 @@ ls_status ls_autotune(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_stre
         return fail(C, LS_ERR_HIP, "hipEventCreate failed");
     }
     static const uint32_t fanouts[] = {512, 1024, 2048, 4096};
-    static const uint32_t tiles[] = {2048, 4096};
+    static const uint32_t tiles[] = {2048, 0};   // 0: automatic (4096, or 8192 in large rounds)
     static const uint32_t bases[] = {1024, 2048, 4096};
     size_t k = 0;
     double best_ms = -1.0;

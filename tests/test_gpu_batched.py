@@ -65,6 +65,7 @@ def test_autotune_keeps_input_and_picks_a_candidate(S):
     torch.cuda.synchronize()
     assert np.array_equal(download(t), before)          # tuning works on a copy
     assert len(results) == 24
+    assert {r["tile"] for r in results} == {2048, 0}         # 0: the automatic tile
     run = [r for r in results if r["ms"] >= 0]
     assert run, results
     fastest = min(run, key=lambda r: r["ms"])
