@@ -158,9 +158,11 @@ def test_wide_tile_rounds_match_the_definition(S):
     # the automatic tile scatters rounds of at least 2^25 keys in 8192-key
     # tiles (the round-0 task here, and the over-full buckets after it);
     # a fixed 4096-key tile must give the same words
+    # fanout 2048 still leaves LDS room for the wide tile, fanout 4096 does
+    # not (those rounds keep 4096-key tiles)
     a = W.zipf_lognormal((1 << 25) + 12_345, seed=14, distinct=400_000)
     want = expected_sorted(a)
-    for kw in (dict(), dict(tile=4096)):
+    for kw in (dict(), dict(tile=4096), dict(fanout=2048), dict(fanout=4096, leaves=512)):
         print("wide tile n=%d params=%s" % (a.size, kw), flush=True)
         got = gpu_sort(S, a, ls.params(**kw))
         assert np.array_equal(got, want)
