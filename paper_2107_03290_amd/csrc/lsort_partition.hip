@@ -661,19 +661,6 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
             G.dtype = T.dtype;
             const uint32_t c = G.n <= kGroupClassCap[0] ? 0u : (G.n <= kGroupClassCap[1] ? 1u : 2u);
             groups.g[c][s_gb[c] + cidx[c][b]] = G;
-        } else if (k == kFillB) {
-            const uint64_t raw = from_ord(bstat[2 * ((uint64_t)T.bucket_off + b)], T.dtype);
-            const uint32_t np = (uint32_t)((sz + kFillPiece - 1) / kFillPiece);
-            for (uint32_t q = 0; q < np; ++q) {
-                Fill F;
-                const uint64_t off = (uint64_t)q * kFillPiece;
-                F.dst = T.keys + T.start + bst[b] + off;
-                F.raw = raw;
-                F.start = T.start + bst[b] + off;
-                F.n = (uint32_t)min((uint64_t)kFillPiece, sz - off);
-                F.dtype = T.dtype;
-                fills[s_fb + fidx[b] + q] = F;
-            }
         } else if (k == kBig) {
             Task C = T;
             C.start = T.start + bst[b];
@@ -712,6 +699,29 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
             }
             next[s_tb + tidx[b]] = C;
         }
+    }
+    // Fill pieces, spread over the workgroup (one all-equal bucket of a
+    // skewed input can hold hundreds of pieces): piece q belongs to the last
+    // bucket whose first piece fidx[b] is at most q.
+    for (uint32_t q = over ? nf : threadIdx.x; q < nf; q += blockDim.x) {
+        uint32_t lo = 0, hi = f;           // fidx[lo] <= q; the answer is below hi
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (fidx[mid] <= q)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const uint32_t b = lo;
+        const uint64_t sz = bst[b + 1] - bst[b];
+        const uint64_t off = (uint64_t)(q - fidx[b]) * kFillPiece;
+        Fill F;
+        F.dst = T.keys + T.start + bst[b] + off;
+        F.raw = from_ord(bstat[2 * ((uint64_t)T.bucket_off + b)], T.dtype);
+        F.start = T.start + bst[b] + off;
+        F.n = (uint32_t)min((uint64_t)kFillPiece, sz - off);
+        F.dtype = T.dtype;
+        fills[s_fb + q] = F;
     }
     // The last workgroup to finish lays out the next round.
     __shared__ uint32_t s_last;
