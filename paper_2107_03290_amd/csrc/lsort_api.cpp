@@ -103,6 +103,8 @@ struct ls_ctx {
     PinBuf estage;                   // round-0 lists of a host-driven sort (read by the upload kernel)
     RoundCtl* h_ctl = nullptr;       // pinned, device-mapped: kernels publish the control block here
     RoundCtl* d_h_ctl = nullptr;     // its device address
+    uint64_t* h_flag = nullptr;      // pinned, device-mapped: set once a layout has published h_ctl
+    uint64_t* d_h_flag = nullptr;
     uint64_t stats[8] = {0};
     uint32_t dev_status = 0;
     size_t lds_limit = 65536;
@@ -442,12 +444,38 @@ ls_status read_ctl(ls_ctx* C, hipStream_t st)
     return LS_OK;
 }
 
-// The layout (alone, or at the end of classify) already wrote the control
-// block into mapped host memory: only wait for the stream.
-ls_status wait_ctl(ls_ctx* C, hipStream_t st)
+// The layout (alone, or at the end of classify) writes the control block
+// into mapped host memory and then sets a flag there.
+//
+// Clear the publish flag before launching a layout that sets it.
+void arm_publish(ls_ctx* C)
 {
-    HIPCHECK(C, hipStreamSynchronize(st));
-    return LS_OK;
+    __atomic_store_n(C->h_flag, 0ull, __ATOMIC_RELEASE);
+}
+
+// Wait until the layout has published the control block (its flag is set),
+// not for the whole stream: the round's scatter may still run while the host
+// reads the next round's sizes and queues its launches behind it.  If the
+// stream drains (or fails) without the flag, the wait ends with an error.
+ls_status wait_published(ls_ctx* C, hipStream_t st)
+{
+    for (uint32_t spin = 1;; ++spin) {
+        if (__atomic_load_n(C->h_flag, __ATOMIC_ACQUIRE))
+            return LS_OK;
+        if (spin % 4096 == 0) {
+            const hipError_t e = hipStreamQuery(st);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(C->h_flag, __ATOMIC_ACQUIRE))
+                    return LS_OK;
+                return fail(C, LS_ERR_HIP, "the control block was not published");
+            }
+            if (e != hipErrorNotReady) {
+                (void)hipGetLastError();
+                return fail(C, LS_ERR_HIP, std::string("stream failed: ") + hipGetErrorString(e));
+            }
+        }
+        __builtin_ia32_pause();
+    }
 }
 
 // Round-0 work of a batch: small arrays go straight to the base case, large
@@ -593,6 +621,9 @@ ls_status check_overflow(ls_ctx* C)
 // from the control block the previous layout published.
 ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams lp, uint32_t flags, Prof& prof)
 {
+    // each layout sets the flag once the control block is published; the
+    // profile's events are read at the end of the sort, when all are done
+    lp.host_flag = C->d_h_flag;
     while (C->h_ctl->ntasks) {
         const RoundCtl R = *C->h_ctl;
         const uint32_t nt = R.ntasks;
@@ -645,6 +676,7 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
                                 nullptr, st));
         prof.end((double)R.entries * 16.0);
         prof.begin(3);
+        arm_publish(C);
         HIPCHECK(C, launch_classify((const Task*)C->tasks.p, nt, (const uint64_t*)C->pos.p,
                                     (const uint64_t*)C->bstat.p, P.base, P.fanout, (Task*)C->next.p, gl,
                                     (Fill*)C->fills.p, (uint8_t*)C->skip.p, (uint32_t*)C->tflags.p,
@@ -656,7 +688,7 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
                                    (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
                                    (const uint32_t*)C->tflags.p, R.tile, R.max_fanout, nullptr, st));
         prof.end(0.0);
-        TRY(wait_ctl(C, st));
+        TRY(wait_published(C, st));
         if (prof.on && !prof.recs.empty()) {
             // scatter: reads every key (and its bucket id) of a task that
             // progressed, writes those not in all-equal buckets
@@ -664,7 +696,6 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
             const double kept = moved - (double)(C->h_ctl->fillkeys - R.fillkeys);
             prof.recs.back().bytes = 10.0 * moved + 8.0 * kept;
         }
-        prof.collect();
         TRY(check_overflow(C));
     }
     return LS_OK;
@@ -1102,13 +1133,15 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
                   B.tr.max_sample, 0, B.tr.models, st, &prof));
     const LayoutParams lp = layout_params(P, global_models);
     if (!B.tasks.empty()) {
-        HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp, (RoundCtl*)C->ctl.p, C->d_h_ctl,
+        LayoutParams lp0 = lp;
+        lp0.host_flag = C->d_h_flag;
+        arm_publish(C);
+        HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp0, (RoundCtl*)C->ctl.p, C->d_h_ctl,
                                   st));
-        TRY(wait_ctl(C, st));
+        TRY(wait_published(C, st));
     } else {
         TRY(read_ctl(C, st));
     }
-    prof.collect();
     const uint32_t flags = msd_only ? 0u : (P.flags & LS_FLAG_NONMONOTONE);
     TRY(rounds_eager(C, st, P, lp, flags, prof));
     TRY(finish_eager(C, st, P, prof, B.group0_keys));
@@ -1173,10 +1206,18 @@ ls_status ls_create(ls_ctx** out, int device)
         C->lds_limit = prop.sharedMemPerBlock;
     if (hipHostMalloc((void**)&C->h_ctl, sizeof(RoundCtl), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||
-        hipHostGetDevicePointer((void**)&C->d_h_ctl, C->h_ctl, 0) != hipSuccess) {
+        hipHostGetDevicePointer((void**)&C->d_h_ctl, C->h_ctl, 0) != hipSuccess ||
+        hipHostMalloc((void**)&C->h_flag, sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void**)&C->d_h_flag, C->h_flag, 0) != hipSuccess) {
+        if (C->h_ctl)
+            (void)hipHostFree(C->h_ctl);
+        if (C->h_flag)
+            (void)hipHostFree(C->h_flag);
         delete C;
         return LS_ERR_NOMEM;
     }
+    *C->h_flag = 0;
     *out = C;
     return LS_OK;
 }
@@ -1201,6 +1242,8 @@ ls_status ls_destroy(ls_ctx* C)
             (void)hipHostFree(b->p);
     if (C->h_ctl)
         (void)hipHostFree(C->h_ctl);
+    if (C->h_flag)
+        (void)hipHostFree(C->h_flag);
     for (hipEvent_t e : C->ev_pool)
         (void)hipEventDestroy(e);
     drop_graphs(C, true);

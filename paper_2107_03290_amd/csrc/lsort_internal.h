@@ -111,6 +111,10 @@ struct LayoutParams {
     // buffers from bounds, so this only guards memory.
     uint64_t cap_tasks, cap_fills, cap_groups[kGroupClasses];
     uint64_t cap_keys, cap_chunks, cap_buckets, cap_entries, cap_samples, cap_blocks, cap_leafs, cap_models;
+    // Mapped host word set to 1 once the control block is published (null:
+    // none).  The host then reads the next round's sizes and queues its
+    // launches while the rest of the round (the scatter) still runs.
+    uint64_t* host_flag;
 };
 
 // Sizes of the running round, copied from the control block when the round

@@ -474,6 +474,12 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
     for (uint32_t i = threadIdx.x; i < kWords; i += NT)
         dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __threadfence_system();
+    if (lp.host_flag) {
+        // every lane's words are out before the flag
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(lp.host_flag, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_layout(Task* tasks, ModelJob* jobs, LayoutParams lp, RoundCtl* ctl,
