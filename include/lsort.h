@@ -56,6 +56,10 @@ typedef enum { LS_F64 = 1, LS_U64 = 2 } ls_dtype;
 #define LS_FLAG_SYNC           0x2u   /* wait for the stream before returning */
 #define LS_FLAG_NONMONOTONE    0x4u   /* test hook: perturb predictions so buckets overlap; the touch-up must repair */
 #define LS_FLAG_PROFILE        0x8u   /* time each kernel class with HIP events (read with ls_last_profile) */
+/* With LS_FLAG_PROFILE: time only kernel class k (0..7, the classes of
+ * ls_last_profile).  Each event pair costs the stream a few microseconds at
+ * a class boundary; with this bit the other classes run back to back. */
+#define LS_FLAG_PROFILE_ONLY(k) (((uint32_t)(k) + 1u) << 8)
 #define LS_FLAG_GRAPH          0x10u  /* run a batch of at most 2^22 keys and 2^16 arrays as one replay of a HIP
                                          graph captured for its size class (keys and arrays rounded up to powers
                                          of two); the first batch of a class captures it.  Results are the same

@@ -27,6 +27,11 @@ FLAG_NONMONOTONE = 0x4
 FLAG_PROFILE = 0x8
 FLAG_GRAPH = 0x10
 
+
+def FLAG_PROFILE_ONLY(k: int) -> int:
+    """With FLAG_PROFILE: time only kernel class k (an index of KERNEL_CLASSES)."""
+    return (k + 1) << 8
+
 KERNEL_CLASSES = ("train", "hist", "scan", "classify", "scatter", "base", "fill", "touchup")
 
 DEV_SEAM_REPAIRED = 0x1

@@ -287,6 +287,8 @@ struct Prof {
         double bytes;
     };
     std::vector<Rec> recs;
+    int only = -1;        // time only this class (LS_FLAG_PROFILE_ONLY), -1: all
+    bool open = false;    // the last begin() recorded an event
     hipEvent_t ev()
     {
         if (C->ev_used == C->ev_pool.size()) {
@@ -299,16 +301,20 @@ struct Prof {
     }
     void begin(int k)
     {
-        if (!on)
+        open = false;
+        if (!on || (only >= 0 && k != only))
             return;
         Rec r{k, ev(), ev(), 0.0};
-        if (r.a && r.b && hipEventRecord(r.a, st) == hipSuccess)
+        if (r.a && r.b && hipEventRecord(r.a, st) == hipSuccess) {
             recs.push_back(r);
+            open = true;
+        }
     }
     void end(double bytes)
     {
-        if (!on || recs.empty())
+        if (!open)
             return;
+        open = false;
         recs.back().bytes = bytes;
         (void)hipEventRecord(recs.back().b, st);
     }
@@ -348,6 +354,8 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
         else P.tile_wide = 2 * kDefaultTile;
         if (p->base_threshold) P.base = p->base_threshold;
         P.flags = p->flags;
+        if (((P.flags >> 8) & 0xfu) > 8u)
+            return fail(C, LS_ERR_INVALID, "LS_FLAG_PROFILE_ONLY takes a kernel class 0..7");
         if (p->sample_rate != 0.0) P.rate = p->sample_rate;
         P.cap = p->sample_cap;
         if (p->seed) P.seed = p->seed;
@@ -683,13 +691,14 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
                                     (RoundCtl*)C->ctl.p, R.max_fanout, (ModelJob*)C->ljobs.p, lp, C->d_h_ctl,
                                     nullptr, st));
         prof.end((double)R.buckets * 32.0);
+        const size_t scatter_rec = prof.recs.size();
         prof.begin(4);
         HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const uint16_t*)C->ids.p,
                                    (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
                                    (const uint32_t*)C->tflags.p, R.tile, R.max_fanout, nullptr, st));
         prof.end(0.0);
         TRY(wait_published(C, st));
-        if (prof.on && !prof.recs.empty()) {
+        if (prof.recs.size() > scatter_rec) {
             // scatter: reads every key (and its bucket id) of a task that
             // progressed, writes those not in all-equal buckets
             const double moved = (double)(R.nkeys - (C->h_ctl->stall_keys - R.stall_keys));
@@ -1116,6 +1125,7 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
     prepare(arrays, C->scratch.p, P, msd_only, B);
     const uint64_t global_models = B.tr.models;
     Prof prof{C, st, (P.flags & LS_FLAG_PROFILE) != 0, {}};
+    prof.only = (int)((P.flags >> 8) & 0xfu) - 1;
 
     // round-0 lists: staged in mapped host memory, copied by one kernel
     const uint64_t ng0[kGroupClasses] = {B.groups0[0].size(), B.groups0[1].size(), B.groups0[2].size()};

@@ -59,3 +59,11 @@ def test_null_arguments_rejected_before_any_launch():
 def test_built_for_gfx950():
     data = open(ls.LIB_PATH, "rb").read()
     assert b"gfx950" in data
+
+
+def test_profile_only_flag_encoding_host_only():
+    # LS_FLAG_PROFILE_ONLY(k) of include/lsort.h: class k + 1 in bits 8..11
+    assert [ls.FLAG_PROFILE_ONLY(k) for k in range(8)] == [(k + 1) << 8 for k in range(8)]
+    assert ls.KERNEL_CLASSES.index("scatter") == 4
+    hdr = open(os.path.join(os.path.dirname(ls.LIB_PATH), "..", "include", "lsort.h")).read()
+    assert "#define LS_FLAG_PROFILE_ONLY(k) (((uint32_t)(k) + 1u) << 8)" in hdr

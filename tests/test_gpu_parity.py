@@ -177,6 +177,30 @@ def test_tile_that_does_not_fit_is_rejected(S):
         S.sort_(t, ls.params(tile=3000))
 
 
+def test_profile_all_classes_and_one_class(S):
+    # every class timed, then the scatter alone; neither changes the result
+    a = inputs("zipf", 2_000_000, 31)
+    want = expected_sorted(a)
+    S.profile_reset()
+    assert np.array_equal(gpu_sort(S, a, ls.params(flags=ls.FLAG_PROFILE)), want)
+    full = S.profile()
+    for k in ("train", "hist", "scan", "classify", "scatter", "base", "touchup"):
+        assert full[k][0] > 0 and full[k][1] > 0, k
+    rounds = S.last_stats()["rounds"]
+    assert full["scatter"][1] == rounds and full["hist"][1] == rounds
+    assert full["scatter"][2] > 0
+    S.profile_reset()
+    only = ls.FLAG_PROFILE | ls.FLAG_PROFILE_ONLY(ls.KERNEL_CLASSES.index("scatter"))
+    assert np.array_equal(gpu_sort(S, a, ls.params(flags=only)), want)
+    one = S.profile()
+    # (local models sample by position, so the round count may differ between two sorts)
+    assert one["scatter"][1] == S.last_stats()["rounds"] and one["scatter"][2] > 0
+    assert all(one[k][1] == 0 for k in ls.KERNEL_CLASSES if k != "scatter")
+    t = torch.zeros(10, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ls.LsortError):
+        S.sort_(t, ls.params(flags=ls.FLAG_PROFILE | (9 << 8)))
+
+
 def test_debug_touchup_full_check(S):
     a = inputs("zipf", 300_000, 8)
     got = gpu_sort(S, a, ls.params(flags=ls.FLAG_DEBUG_TOUCHUP))
