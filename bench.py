@@ -72,7 +72,7 @@ def cpu_baseline(a: np.ndarray, sample: int):
 
 
 def cpu_library_sort(a: np.ndarray, sample: int):
-    """numpy's introsort (one thread) on the order-preserving words of the
+    """numpy's default sort (one thread) on the order-preserving words of the
     same sample: a comparison-sort reference beside the oracle."""
     w = np.ascontiguousarray(a[:sample]).view(np.uint64)
     if a.dtype == np.float64:
@@ -83,7 +83,7 @@ def cpu_library_sort(a: np.ndarray, sample: int):
     t0 = time.perf_counter()
     w.sort(kind="quicksort")
     dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "keys/s", "cores": 1, "kind": "numpy introsort on order words",
+    return {"value": sample / dt, "unit": "keys/s", "cores": 1, "kind": "numpy sort on order words",
             "sample": "first %d keys, %.1f s" % (sample, dt)}
 
 
