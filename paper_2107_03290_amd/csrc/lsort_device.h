@@ -151,6 +151,10 @@ __device__ __forceinline__ double model_F(const SModel& M, uint64_t raw)
     uint32_t j = k;
     double2 a = M.seg[2 * k];         // {X, ylo}
     double2 b = M.seg[2 * k + 1];     // {s, yhi}
+    // Keep the whole segment loaded here: otherwise the compiler moves the
+    // loads of ylo, s and yhi past the branch (they are dead on its taken
+    // side), and the common path pays a second dependent LDS round trip.
+    asm volatile("" : "+v"(a.y), "+v"(b.x), "+v"(b.y));
     if (x < a.x) {                    // below this leaf's knot: previous knot
         j = M.prev[k];
         a = M.seg[2 * j];
