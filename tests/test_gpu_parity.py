@@ -162,7 +162,8 @@ def test_wide_tile_rounds_match_the_definition(S):
     # not (those rounds keep 4096-key tiles)
     a = W.zipf_lognormal((1 << 25) + 12_345, seed=14, distinct=400_000)
     want = expected_sorted(a)
-    for kw in (dict(), dict(tile=4096), dict(fanout=2048), dict(fanout=4096, leaves=512)):
+    # (fanout 3072 takes the most LDS a wide tile may: 8192 * 10 + 3072 * 24 bytes)
+    for kw in (dict(), dict(tile=4096), dict(fanout=2048), dict(fanout=3072), dict(fanout=4096, leaves=512)):
         print("wide tile n=%d params=%s" % (a.size, kw), flush=True)
         got = gpu_sort(S, a, ls.params(**kw))
         assert np.array_equal(got, want)
@@ -196,6 +197,14 @@ def test_profile_all_classes_and_one_class(S):
     # (local models sample by position, so the round count may differ between two sorts)
     assert one["scatter"][1] == S.last_stats()["rounds"] and one["scatter"][2] > 0
     assert all(one[k][1] == 0 for k in ls.KERNEL_CLASSES if k != "scatter")
+    # each class alone: its own launches only, and the same words
+    for k, name in enumerate(ls.KERNEL_CLASSES):
+        S.profile_reset()
+        got = gpu_sort(S, a, ls.params(flags=ls.FLAG_PROFILE | ls.FLAG_PROFILE_ONLY(k)))
+        assert np.array_equal(got, want), name
+        prof = S.profile()
+        assert prof[name][1] > 0 or full[name][1] == 0, name
+        assert all(prof[c][1] == 0 for c in ls.KERNEL_CLASSES if c != name), name
     t = torch.zeros(10, dtype=torch.float64, device="cuda:0")
     with pytest.raises(ls.LsortError):
         S.sort_(t, ls.params(flags=ls.FLAG_PROFILE | (9 << 8)))
