@@ -276,7 +276,8 @@ ls_status upload(ls_ctx* C, PinBuf& pin, DevBuf& dst, const std::vector<T>& v, h
     return LS_OK;
 }
 
-// Event pairs for one kernel class; read back after the next stream sync.
+// Event pairs around the launches of the kernel classes being timed; read
+// back at the end of the sort, after its final stream sync.
 struct Prof {
     ls_ctx* C;
     hipStream_t st;
@@ -318,7 +319,7 @@ struct Prof {
         recs.back().bytes = bytes;
         (void)hipEventRecord(recs.back().b, st);
     }
-    // after a stream sync
+    // after the final stream sync of the sort (every event is complete)
     void collect()
     {
         for (auto& r : recs) {
