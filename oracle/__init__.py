@@ -96,6 +96,9 @@ def lib() -> ctypes.CDLL:
                                      ctypes.c_uint64]
         L.orc_counting_sort.argtypes = [u64p, ctypes.c_size_t, dp, ctypes.c_uint32,
                                         ctypes.c_uint32, ctypes.c_double, ctypes.c_double]
+        L.orc_split_stage.argtypes = [u64p, ctypes.c_size_t, P(Params), ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_int, u64p, u64p, ctypes.c_uint32, P(ctypes.c_uint32),
+                                      P(ctypes.c_uint32), P(ctypes.c_uint32)]
         L.orc_insertion_sort.argtypes = [u64p, ctypes.c_size_t, ctypes.c_uint32]
         L.orc_insertion_sort.restype = ctypes.c_uint64
         _lib = L
@@ -249,6 +252,26 @@ def counting_sort(keys: np.ndarray, model: np.ndarray, leaves: int, scale: float
     if rc != 0:
         raise RuntimeError("oracle counting sort failed: %d" % rc)
     return w.view(np.float64) if dt == F64 else w
+
+
+DEPTH_ERROR = -5
+
+
+def split_stage(keys: np.ndarray, start: int = 0, depth: int = 2, force_msd: bool = False, **kw) -> dict:
+    """One recursion split of reading R18 on a copy of keys (at least two
+    distinct): {"keys": the range after the split, "sb": child sizes,
+    "msd": whether the MSD digit split it, "shift": that digit's shift}."""
+    w, dt = as_words(keys)
+    p = params(dt, **kw)
+    out = np.zeros(w.size, np.uint64)
+    sb = np.zeros(p.fanout, np.uint64)
+    fo, msd, sh = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    rc = lib().orc_split_stage(_u64(w), w.size, ctypes.byref(p), start, depth, int(force_msd), _u64(out),
+                               _u64(sb), p.fanout, ctypes.byref(fo), ctypes.byref(msd), ctypes.byref(sh))
+    if rc != 0:
+        raise RuntimeError("oracle split failed: %d" % rc)
+    return {"keys": out.view(np.float64) if dt == F64 else out, "sb": sb[: fo.value], "msd": bool(msd.value),
+            "shift": int(sh.value)}
 
 
 def insertion_sort(keys: np.ndarray) -> tuple[np.ndarray, int]:

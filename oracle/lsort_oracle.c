@@ -30,8 +30,10 @@
  *   R16    sample with replacement, m = max(1, ceil(rate*n)).
  *   R17    n <= 1: nothing; n <= small_n: insertion sort.
  *   R18    optional recursion (s_max > 0) into over-full sub-buckets with a
- *          local model; a partition that leaves every key in one bucket is
- *          redone on the highest differing bit (MSD fallback).
+ *          local model; a partition that leaves more than 7/8 of the keys
+ *          in one bucket is redone on the bits just below the highest
+ *          differing bit (MSD fallback); past a provable depth bound the
+ *          sort stops with ORC_ERR_DEPTH.
  *   R20    non-finite f64 keys: F = 0 for negative, 1 for positive.
  *   R24    u64 -> f64 conversion rounds to nearest even.
  */
@@ -618,6 +620,7 @@ typedef struct {
     orc_stats* st;
     uint32_t f, c, L, dtype;
     uint64_t s_max;
+    uint32_t depth_max;  /* deepest recursion level allowed (depth_bound) */
 } ctx_t;
 
 static uint64_t local_seed(uint64_t seed, uint64_t start, uint32_t depth)
@@ -633,6 +636,7 @@ static uint64_t local_sample_size(const ctx_t* C, uint64_t n)
 }
 
 static int recurse_local(const ctx_t* C, uint64_t* A, uint64_t n, uint64_t start, uint32_t depth);
+static uint32_t depth_bound(uint64_t n);
 
 /* Base case of a range no model bucket covers (children of an MSD split):
  * train a local model on the range and counting-sort by F * n. */
@@ -675,50 +679,91 @@ static int partition_defrag(const ctx_t* C, uint64_t* A, uint64_t n, const bucke
     return rc;
 }
 
+/* Highest differing bit of a range's extreme words: the MSD fallback of
+ * reading R18 partitions on the bits just below it. */
+static void range_extremes(const uint64_t* A, uint64_t n, uint64_t* lo, uint64_t* hi)
+{
+    *lo = ~0ull;
+    *hi = 0;
+    for (uint64_t k = 0; k < n; ++k) {
+        if (A[k] < *lo) *lo = A[k];
+        if (A[k] > *hi) *hi = A[k];
+    }
+}
+
+/* The MSD digit of reading R18 for a range whose extremes differ first at
+ * bit d: the b' = min(floor(log2 f), d+1) bits at [d+1-b', d] of the word.
+ * Keys of the range agree above bit d, so the digit is monotone in the word,
+ * and lo and hi get different digits (their bit d differs). */
+static void msd_bucketer(bucketer_t* B, uint64_t lo, uint64_t hi, uint32_t f)
+{
+    uint32_t d = 63u - (uint32_t)__builtin_clzll(lo ^ hi);
+    uint32_t lf = 0;
+    while ((1u << (lf + 1)) <= f)
+        ++lf;                                 /* floor(log2 f) */
+    uint32_t bits = lf < d + 1 ? lf : d + 1;
+    if (bits == 0)
+        bits = 1;
+    B->kind = BK_MSD;
+    B->fanout = 1u << bits;
+    B->shift = d + 1 - bits;
+    B->mask = (1ull << bits) - 1u;
+}
+
+/* One split of reading R18 on a non-homogeneous range A[0..n): Partition +
+ * Defragment by a local model trained on the range (Sec. 2's eCDF model on
+ * a sample of the range).  When the largest bucket still holds more than
+ * 7/8 of the keys the model made no real progress, and the range is
+ * partitioned again on its MSD digit instead (force_msd: directly).  Every
+ * child of a model split then holds at most 7/8 of the range, and every
+ * child of an MSD split differs first at a lower bit than the range, which
+ * bounds the depth (see depth_bound).  B, SB (C->f entries) and M (model
+ * storage, freed by the caller when B->kind == BK_MODEL) receive the split. */
+static int split_range(const ctx_t* C, uint64_t* A, uint64_t n, uint64_t start, uint32_t depth,
+                       int force_msd, model_t* M, bucketer_t* B, uint64_t* SB)
+{
+    int rc = ORC_OK;
+    memset(M, 0, sizeof *M);
+    uint64_t biggest = n;
+    if (!force_msd) {
+        rc = model_fit_range(M, A, n, local_sample_size(C, n), local_seed(C->p->seed, start, depth),
+                             C->L, C->dtype, NULL);
+        if (rc)
+            return rc;
+        bucketer_t BM = {BK_MODEL, M, C->dtype, (double)C->f, 0, C->f, 0, 0};
+        *B = BM;
+        rc = partition_defrag(C, A, n, B, SB);
+        biggest = 0;
+        for (uint32_t j = 0; j < C->f; ++j)
+            if (SB[j] > biggest)
+                biggest = SB[j];
+    }
+    if (rc == ORC_OK && 8 * biggest > 7 * n) {
+        uint64_t lo, hi;
+        range_extremes(A, n, &lo, &hi);
+        msd_bucketer(B, lo, hi, C->f);
+        B->M = M;
+        C->st->fallbacks++;
+        rc = partition_defrag(C, A, n, B, SB);
+    }
+    return rc;
+}
+
 /* Reading R18: recursion into an over-full, non-homogeneous range. */
 static int recurse_local(const ctx_t* C, uint64_t* A, uint64_t n, uint64_t start, uint32_t depth)
 {
     if (n <= 1 || homogeneous(A, n))
         return ORC_OK;
+    if (depth > C->depth_max)
+        return ORC_ERR_DEPTH;
     if (depth > C->st->max_depth)
         C->st->max_depth = depth;
-    model_t M;
-    int rc = model_fit_range(&M, A, n, local_sample_size(C, n), local_seed(C->p->seed, start, depth),
-                             C->L, C->dtype, NULL);
-    if (rc)
-        return rc;
-    bucketer_t B = {BK_MODEL, &M, C->dtype, (double)C->f, 0, C->f, 0, 0};
     uint64_t* SB = (uint64_t*)malloc((size_t)C->f * sizeof(uint64_t));
-    if (!SB) {
-        model_free(&M);
+    if (!SB)
         return ORC_ERR_NOMEM;
-    }
-    rc = partition_defrag(C, A, n, &B, SB);
-    uint64_t biggest = 0;
-    for (uint32_t j = 0; j < C->f; ++j)
-        if (SB[j] > biggest)
-            biggest = SB[j];
-    if (rc == ORC_OK && biggest == n) {
-        /* No progress: split on the highest bit where the range differs. */
-        uint64_t lo = ~0ull, hi = 0;
-        for (uint64_t k = 0; k < n; ++k) {
-            if (A[k] < lo) lo = A[k];
-            if (A[k] > hi) hi = A[k];
-        }
-        uint32_t d = 63u - (uint32_t)__builtin_clzll(lo ^ hi);
-        uint32_t lf = 0;
-        while ((1u << (lf + 1)) <= C->f)
-            ++lf;                                 /* floor(log2 f) */
-        uint32_t bits = lf < d + 1 ? lf : d + 1;
-        if (bits == 0)
-            bits = 1;
-        B.kind = BK_MSD;
-        B.fanout = 1u << bits;
-        B.shift = d + 1 - bits;
-        B.mask = (1ull << bits) - 1u;
-        C->st->fallbacks++;
-        rc = partition_defrag(C, A, n, &B, SB);
-    }
+    model_t M;
+    bucketer_t B;
+    int rc = split_range(C, A, n, start, depth, 0, &M, &B, SB);
     uint64_t r = 0;
     for (uint32_t j = 0; j < B.fanout && rc == ORC_OK; ++j) {
         rc = finish_child(C, A + r, SB[j], start + r, depth, &B, j);
@@ -727,6 +772,18 @@ static int recurse_local(const ctx_t* C, uint64_t* A, uint64_t n, uint64_t start
     free(SB);
     model_free(&M);
     return rc;
+}
+
+/* Deepest level a sort of n keys may reach: levels 0 and 1, then at most
+ * ceil(log_{8/7} n) <= 6 ceil(log2 n) model splits (each child keeps at most
+ * 7/8 of its range) and at most 64 MSD splits (each lowers the highest bit
+ * in which a range's keys differ). */
+static uint32_t depth_bound(uint64_t n)
+{
+    uint32_t lg = 0;
+    while (lg < 64 && (1ull << lg) < n)
+        ++lg;
+    return 2u + 64u + 6u * lg;
 }
 
 void orc_default_params(orc_params* p, uint32_t dtype)
@@ -825,7 +882,7 @@ int orc_sort(uint64_t* keys, size_t n, const orc_params* p, orc_stats* st)
         st->status = ORC_ERR_ARG;
         return ORC_ERR_ARG;
     }
-    ctx_t C = {p, st, p->fanout, p->frag_cap, p->leaves, p->dtype, p->s_max};
+    ctx_t C = {p, st, p->fanout, p->frag_cap, p->leaves, p->dtype, p->s_max, depth_bound(n)};
     for (size_t k = 0; k < n; ++k)
         keys[k] = raw_to_ord(keys[k], p->dtype);
     rc = learned_sort(&C, keys, n);
@@ -983,7 +1040,7 @@ int orc_stage_level0(const uint64_t* keys, size_t n, const orc_params* p,
     uint32_t f = p->fanout;
     orc_stats st;
     memset(&st, 0, sizeof st);
-    ctx_t C = {p, &st, f, p->frag_cap, p->leaves, p->dtype, p->s_max};
+    ctx_t C = {p, &st, f, p->frag_cap, p->leaves, p->dtype, p->s_max, depth_bound(n)};
     uint64_t* A = to_ord_copy(keys, n, p->dtype);
     uint64_t* SB = (uint64_t*)malloc((size_t)f * sizeof(uint64_t));
     uint64_t* SB1 = (uint64_t*)malloc((size_t)f * sizeof(uint64_t));
@@ -1063,5 +1120,43 @@ int orc_stage_level0(const uint64_t* keys, size_t n, const orc_params* p,
     free(A);
     free(SB);
     free(SB1);
+    return rc;
+}
+
+int orc_split_stage(const uint64_t* keys, size_t n, const orc_params* p, uint64_t start, uint32_t depth,
+                    int force_msd, uint64_t* out_keys, uint64_t* sb, uint32_t sb_cap, uint32_t* fanout_out,
+                    uint32_t* msd_out, uint32_t* shift_out)
+{
+    if (check_params(p) || !keys || n < 2 || !sb || sb_cap < p->fanout)
+        return ORC_ERR_ARG;
+    orc_stats st;
+    memset(&st, 0, sizeof st);
+    ctx_t C = {p, &st, p->fanout, p->frag_cap, p->leaves, p->dtype, p->s_max, depth_bound(n)};
+    uint64_t* A = to_ord_copy(keys, n, p->dtype);
+    uint64_t* SB = (uint64_t*)calloc(p->fanout, sizeof(uint64_t));
+    if (!A || !SB) {
+        free(A);
+        free(SB);
+        return ORC_ERR_NOMEM;
+    }
+    int rc = homogeneous(A, n) ? ORC_ERR_ARG : ORC_OK;
+    model_t M;
+    memset(&M, 0, sizeof M);
+    bucketer_t B;
+    if (rc == ORC_OK)
+        rc = split_range(&C, A, n, start, depth, force_msd, &M, &B, SB);
+    if (rc == ORC_OK) {
+        memset(sb, 0, (size_t)sb_cap * sizeof(uint64_t));
+        memcpy(sb, SB, (size_t)B.fanout * sizeof(uint64_t));
+        if (fanout_out) *fanout_out = B.fanout;
+        if (msd_out) *msd_out = B.kind == BK_MSD;
+        if (shift_out) *shift_out = B.kind == BK_MSD ? B.shift : 0;
+        if (out_keys)
+            for (size_t k = 0; k < n; ++k)
+                out_keys[k] = ord_to_raw(A[k], p->dtype);
+    }
+    model_free(&M);
+    free(A);
+    free(SB);
     return rc;
 }

@@ -37,6 +37,7 @@ enum {
     ORC_ERR_NOMEM = -2,
     ORC_ERR_WRITE_HEAD = -3,   /* write head overtook the read head (Alg. 1 invariant) */
     ORC_ERR_PARTITION = -4,    /* fragments do not account for every key */
+    ORC_ERR_DEPTH = -5,        /* recursion passed its depth bound (reading R18) */
 };
 
 typedef struct {
@@ -129,6 +130,19 @@ int orc_defragment(uint64_t* keys, size_t n, const uint64_t* sb, uint32_t fanout
  * keys placed. */
 int orc_counting_sort(uint64_t* keys, size_t n, const double* model, uint32_t leaves,
                       uint32_t dtype, double scale, double offset);
+
+/* One recursion split of reading R18 on a copy of keys[0..n) (n >= 2, not
+ * all equal), exactly as the sort takes it for a range at `start` (relative
+ * to the array) and recursion level `depth`: Partition + Defragment by a
+ * local model trained on the range, or, when its largest bucket keeps more
+ * than 7/8 of the keys (or with force_msd), by the MSD digit below the
+ * range's highest differing bit.  Outputs: out_keys[n] (may be NULL) the
+ * range after the split, sb[sb_cap >= fanout] the child sizes (zero past
+ * the split's fanout), *fanout_out the children, *msd_out 1 for an MSD
+ * split, *shift_out its digit's shift. */
+int orc_split_stage(const uint64_t* keys, size_t n, const orc_params* p, uint64_t start, uint32_t depth,
+                    int force_msd, uint64_t* out_keys, uint64_t* sb, uint32_t sb_cap, uint32_t* fanout_out,
+                    uint32_t* msd_out, uint32_t* shift_out);
 
 /* Insertion sort on ord order; returns element moves. */
 uint64_t orc_insertion_sort(uint64_t* keys, size_t n, uint32_t dtype);

@@ -36,6 +36,16 @@ MUTANTS = {
     "counting_sort_slot_from_parent": ("double v = (model_F(M, ord_value(A[k], dtype)) * scale - offset) * (double)n;",
                                        "double v = (model_F(M, ord_value(A[k], dtype)) * scale) * (double)n;"),
     "homogeneous_compares_neighbour_sign": ("if (A[k] != A[0])", "if ((A[k] >> 1) != (A[0] >> 1))"),
+    "msd_digit_reversed": ("return (uint32_t)((o >> B->shift) & B->mask);",
+                           "return (uint32_t)((~o >> B->shift) & B->mask);"),
+    "msd_shift_one_too_high": ("B->shift = d + 1 - bits;", "B->shift = d + 2 - bits;"),
+    "msd_shift_one_too_low": ("B->shift = d + 1 - bits;", "B->shift = d - bits;"),
+    "msd_fallback_never_taken": ("if (rc == ORC_OK && 8 * biggest > 7 * n) {",
+                                 "if (rc == ORC_OK && 8 * biggest > 8 * n) {"),
+    "local_split_at_level1_scale": ("bucketer_t BM = {BK_MODEL, M, C->dtype, (double)C->f, 0, C->f, 0, 0};",
+                                    "bucketer_t BM = {BK_MODEL, M, C->dtype, (double)C->f * C->f, 0, C->f, 0, 0};"),
+    "local_split_buckets_reversed": ("        bucketer_t BM = {BK_MODEL, M, C->dtype, (double)C->f, 0, C->f, 0, 0};",
+                                     "        bucketer_t BM = {BK_MODEL, M, C->dtype, -(double)C->f, -(int64_t)C->f + 1, C->f, 0, 0};"),
     "f64_ord_sign_flip": ("return (b >> 63) ? ~b : (b | 0x8000000000000000ull);",
                           "return (b >> 63) ? (b & 0x7fffffffffffffffull) : (b | 0x8000000000000000ull);"),
 }

@@ -428,11 +428,89 @@ def test_nonfinite_total_order():
 
 def test_no_progress_fallback_u64():
     # Reading R18: keys that round to one double cannot be separated by the
-    # model; the highest-differing-bit split makes progress.
+    # model; the highest-differing-bit split makes progress.  Its two children
+    # (bit 0 = 0, then bit 0 = 1) are each all-equal, so the split alone puts
+    # every key in place and the touch-up has nothing to move.
     a = np.array([2 ** 53, 2 ** 53 + 1] * 3000, dtype=np.uint64)
     np.random.default_rng(3).shuffle(a)
     st = _check(a, s_max=100, fanout=16, leaves=16)
     assert st.fallbacks >= 1
+    assert st.touchup_moves == 0
+
+
+def _split_spans(res: dict, keys: np.ndarray):
+    """(min, max) order word of each non-empty child of a split, after
+    checking that the split is a permutation with the stated sizes."""
+    o = ord_words(res["keys"])
+    assert np.array_equal(np.sort(o), np.sort(ord_words(keys)))
+    sizes = res["sb"].astype(np.int64)
+    assert int(sizes.sum()) == keys.size
+    ends = np.cumsum(sizes)
+    return [(int(o[e - z:e].min()), int(o[e - z:e].max())) for z, e in zip(sizes, ends) if z]
+
+
+def _assert_ordered_and_separating(spans):
+    # every key of a child is <= every key of the next non-empty child
+    for (_, hi0), (lo1, _) in zip(spans, spans[1:]):
+        assert hi0 <= lo1
+    # progress: the range's minimum and maximum end in different children
+    assert len(spans) >= 2
+
+
+# 64 distinct u64 words within half an ulp of 2^62: they all round to the
+# double 2^62, so no model separates them (reading R24).
+NEAR_2_62 = np.uint64(2 ** 62) + np.arange(64, dtype=np.uint64)
+
+
+def test_msd_split_digit_by_hand():
+    # Reading R18 worked by hand: the words differ first at bit d = 5
+    # (0 ^ 63 = 0b111111); with f = 16, b' = min(log2 16, d + 1) = 4 bits at
+    # [2, 5], i.e. shift 2 and digit (w >> 2) & 15.  Value v goes to child
+    # v // 4, so each child holds 4 values x 50 copies = 200 keys.
+    a = np.repeat(NEAR_2_62, 50)
+    np.random.default_rng(5).shuffle(a)
+    res = oracle.split_stage(a, fanout=16, leaves=16)
+    assert res["msd"] and res["shift"] == 2
+    assert res["sb"].tolist() == [200] * 16
+    _assert_ordered_and_separating(_split_spans(res, a))
+
+
+def test_msd_split_on_sign_bit_by_hand():
+    # f64 keys of both signs differ first at bit 63 of their order words;
+    # b' = 4 at [60, 63]: the top nibbles of ord(-2.0) = 0x3FFF..., ord(-1.0)
+    # = 0x400F..., ord(1.0) = 0xBFF0..., ord(2.0) = 0xC000... are 3, 4, 11, 12.
+    a = np.repeat(np.array([2.0, -1.0, 1.0, -2.0]), [5, 7, 11, 13])
+    np.random.default_rng(6).shuffle(a)
+    res = oracle.split_stage(a, force_msd=True, fanout=16, leaves=16)
+    assert res["msd"] and res["shift"] == 60
+    expect = [0] * 16
+    expect[3], expect[4], expect[11], expect[12] = 13, 7, 11, 5
+    assert res["sb"].tolist() == expect
+    _assert_ordered_and_separating(_split_spans(res, a))
+
+
+@pytest.mark.parametrize("family", ["lognormal", "normal", "zipf"])
+def test_local_split_children_ordered(family):
+    # A local model split (reading R18) partitions by a monotone model: its
+    # children are ordered, and a split that keeps its model makes progress
+    # (no child holds more than 7/8 of the range).
+    a = W.paper_family(family, 40_000, seed=17)
+    res = oracle.split_stage(a, start=123, depth=3, fanout=64, leaves=64)
+    assert not res["msd"]
+    assert res["sb"].size == 64
+    assert 8 * int(res["sb"].max()) <= 7 * a.size
+    _assert_ordered_and_separating(_split_spans(res, a))
+
+
+def test_msd_recursion_places_every_key_without_touchup():
+    # Two levels of MSD splits (shift 2, then bits [0, 1]) leave every child
+    # all-equal: the recursion alone sorts, so the touch-up moves nothing.
+    a = np.repeat(NEAR_2_62, 200)
+    np.random.default_rng(7).shuffle(a)
+    st = _check(a, s_max=100, fanout=16, leaves=16)
+    assert st.fallbacks >= 2
+    assert st.touchup_moves == 0
+    assert st.max_depth >= 3
 
 
 def test_recursive_mode_bounds_touchup():
