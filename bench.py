@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
 """Benchmark: LearnedSort 2.0 keys/s on one MI355X.
 
-Default workload: 200,000,000 float64 keys, Zipf(s=1.2) picks among 100,000
-distinct values each drawn lognormal(0, 2) (more than 95% repeats), seeded.
-A step is one complete sort of one copy of that array (sample, train,
-partition rounds, base case, fills, touch-up), inputs resident in HBM.
+Default workload: 1,000,000,000 uint64 keys (8 GB), equal thirds of
+round(N(2^40, 2^36)), round(Exp(scale 2^30)) and U[0, 2^64) mod 10,000 at
+shuffled positions, seeded: the largest single-array configuration, with
+recursion below level 1.  A step is one complete sort of one copy of that
+array (sample, train, partition rounds, base case, fills, touch-up), inputs
+resident in HBM.  Other workloads: --workload zipf_lognormal (2e8 f64,
+Zipf-duplicates), uniform (1e6 f64), segments, served, sweep.
 
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (algorithmic bytes / its HIP-event time, against 8 TB/s) and the CPU
@@ -87,9 +90,14 @@ def cpu_library_sort(a: np.ndarray, sample: int):
             "sample": "first %d keys, %.1f s" % (sample, dt)}
 
 
-def roofline(prof: dict, wname: str) -> dict:
+def roofline(prof: dict, wname: str, overhead: dict | None = None) -> dict:
     """Roofline entry of the dominant kernel class: algorithmic bytes per
-    launch over the average launch time (HIP events on the sort's stream)."""
+    launch over the average launch time (HIP events on the sort's stream).
+    Algorithmic bytes are the method's: the histogram reads 8 B per key, the
+    scatter reads 8 B per key of a progressing range and writes 8 B per key
+    outside all-equal buckets, the base case reads and writes 8 B per key.
+    The design's own extra traffic (2-byte bucket ids) is reported beside
+    it, not in it."""
     dom = max(("hist", "scatter", "base", "fill", "train"), key=lambda k: prof[k][0])
     ms, launches, byt = prof[dom]
     achieved = (byt / launches) / ((ms / launches) / 1e3) / 1e9 if launches else 0.0
@@ -102,6 +110,7 @@ def roofline(prof: dict, wname: str) -> dict:
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "alg_bytes_per_launch": byt / launches if launches else 0.0,
+            "design_overhead_bytes_per_launch": (overhead or {}).get(dom, 0.0) / launches if launches else 0.0,
             "avg_launch_ms": ms / launches if launches else 0.0}
 
 
@@ -205,7 +214,7 @@ def bench_segments(args, torch, ls):
                   "calls": int(off.size - 1), "params": "defaults"},
         "batched_over_plain": ms_p / ms,
         "identical_to_plain": same,
-        "roofline": roofline(prof, "segments_%d_f64" % (off.size - 1)),
+        "roofline": roofline(prof, "segments_%d_f64" % (off.size - 1), S.profile_overhead()),
         "kernel_ms_per_step": breakdown,
         "kernel_ms_source": "%d untimed steps after the warm-up with every kernel class timed; the timed "
                             "steps time the dominant class (%s) only" % (PROFILED_STEPS, dom),
@@ -215,7 +224,8 @@ def bench_segments(args, torch, ls):
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        take = int(np.searchsorted(off, min(args.cpu_sample, n), side="right")) - 1
+        want = args.cpu_sample if args.cpu_sample > 0 else 500_000_000   # about 25 s of oracle work
+        take = int(np.searchsorted(off, min(want, n), side="right")) - 1
         take = max(take, 1)
         t0 = time.perf_counter()
         for i in range(take):
@@ -248,7 +258,10 @@ def bench_served(args, torch, ls):
           file=sys.stderr, flush=True)
     # graph mode (LS_FLAG_GRAPH): requests and batches of up to 2^22 keys run
     # as replays of captured graphs, on the plain path and in the server
-    gp = ls.params(flags=ls.FLAG_GRAPH) if args.graph == "on" else ls.params()
+    if args.graph == "on":
+        raise SystemExit("--graph on is not available for the served workload: the server runs host-driven "
+                         "batches (graph replays in the server are switched off)")
+    gp = ls.params()
     pristine = [to_device(a, torch) for a in reqs]
     work = [torch.empty_like(t) for t in pristine]
     ref = [torch.empty_like(t) for t in pristine]
@@ -436,23 +449,23 @@ def main():
     ap.add_argument("--summarize-trace", help="rocprofv3 database of a --kernel-trace run of this script")
     ap.add_argument("--summarize-fetch", help="rocprofv3 database of a --pmc FETCH_SIZE run")
     ap.add_argument("--summarize-write", help="rocprofv3 database of a --pmc WRITE_SIZE run")
-    ap.add_argument("--workload-name", default="zipf_lognormal_f64")
+    ap.add_argument("--workload-name", default="mixed_u64")
     ap.add_argument("--traffic-kernel", default="scatter")
-    ap.add_argument("--copy-bytes", type=float, default=1.6e9)
+    ap.add_argument("--copy-bytes", type=float, default=8e9)
     ap.add_argument("--trace-command", default="")
     ap.add_argument("--fetch-command", default="")
     ap.add_argument("--write-command", default="")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf_lognormal")
+    ap.add_argument("--workload", default="mixed_u64")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--fanout", type=int, default=0)
     ap.add_argument("--leaves", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--base", type=int, default=0)
     ap.add_argument("--sample-cap", type=int, default=-1, help="cap on a model's sample (-1: library default)")
-    ap.add_argument("--cpu-sample", type=int, default=200_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="keys the CPU oracle sorts (0: the whole array)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verify", action="store_true", help="check the sorted output against numpy")
     ap.add_argument("--segments", type=int, default=10_000, help="arrays of the segments workload")
@@ -549,7 +562,7 @@ def main():
         "config": {"workload": wname, "n": n, "fanout": p.fanout, "leaves": p.leaves,
                    "tile": p.tile or "auto (4096; 8192 in rounds of >= 2^25 keys)",
                    "base_threshold": p.base_threshold, "sample_rate": p.sample_rate, "sample_cap": p.sample_cap},
-        "roofline": roofline(prof, wname),
+        "roofline": roofline(prof, wname, S.profile_overhead()),
         "kernel_ms_per_step": breakdown,
         "kernel_GBps": gbps,
         "kernel_ms_source": "%d untimed steps after the warm-up with every kernel class timed; the timed "
@@ -558,8 +571,9 @@ def main():
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(keys, min(args.cpu_sample, n))
-        line["cpu_library_sort"] = cpu_library_sort(keys, min(args.cpu_sample, n))
+        take = min(args.cpu_sample, n) if args.cpu_sample > 0 else n
+        line["cpu_baseline"] = cpu_baseline(keys, take)
+        line["cpu_library_sort"] = cpu_library_sort(keys, take)
     print(json.dumps(line), flush=True)
     S.close()
 

@@ -169,7 +169,11 @@ ls_status ls_last_stats(ls_ctx* ctx, uint64_t* out8);
 /* Per kernel class, accumulated since the last ls_profile_reset (only for
  * sorts run with LS_FLAG_PROFILE): out[3*k + 0] milliseconds, [3*k + 1]
  * launches, [3*k + 2] algorithmic bytes (keys read + written as the method
- * requires).  Classes k: 0 train, 1 histogram, 2 scan, 3 classify,
+ * requires: the histogram reads each key of a round once, the scatter reads
+ * each key of a progressing range and writes each one outside all-equal
+ * buckets).  With cap >= 32, out[24 + k] receives the bytes the design adds
+ * beyond those (the 2-byte bucket id the histogram writes and the scatter
+ * reads per key).  Classes k: 0 train, 1 histogram, 2 scan, 3 classify,
  * 4 scatter, 5 base case, 6 fill, 7 touch-up.  cap >= 24. */
 ls_status ls_last_profile(ls_ctx* ctx, double* out, size_t cap);
 ls_status ls_profile_reset(ls_ctx* ctx);
@@ -207,7 +211,8 @@ typedef struct ls_server ls_server;
  * they need (keys already resident + the library's scratch) stays within
  * hbm_budget_bytes, batches the admitted ones into segmented sorts, and
  * keeps up to max_inflight batches in flight on separate streams.  p may be
- * NULL (the defaults; batches run host-driven unless p sets LS_FLAG_GRAPH). */
+ * NULL (the defaults).  p->flags with LS_FLAG_GRAPH is rejected with
+ * LS_ERR_UNSUPPORTED: served batches run host-driven. */
 ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
                            uint32_t max_inflight, const ls_params* p);
 

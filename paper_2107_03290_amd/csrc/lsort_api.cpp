@@ -110,6 +110,7 @@ struct ls_ctx {
     size_t lds_limit = 65536;
     // LS_FLAG_PROFILE: event pairs around each kernel class
     double prof_ms[8] = {0}, prof_launch[8] = {0}, prof_bytes[8] = {0};
+    double prof_extra[8] = {0};   // bytes the design moves beyond the method's (the u16 bucket ids)
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     // graph mode
@@ -286,6 +287,7 @@ struct Prof {
         int k;
         hipEvent_t a, b;
         double bytes;
+        double extra;
     };
     std::vector<Rec> recs;
     int only = -1;        // time only this class (LS_FLAG_PROFILE_ONLY), -1: all
@@ -305,18 +307,19 @@ struct Prof {
         open = false;
         if (!on || (only >= 0 && k != only))
             return;
-        Rec r{k, ev(), ev(), 0.0};
+        Rec r{k, ev(), ev(), 0.0, 0.0};
         if (r.a && r.b && hipEventRecord(r.a, st) == hipSuccess) {
             recs.push_back(r);
             open = true;
         }
     }
-    void end(double bytes)
+    void end(double bytes, double extra = 0.0)
     {
         if (!open)
             return;
         open = false;
         recs.back().bytes = bytes;
+        recs.back().extra = extra;
         (void)hipEventRecord(recs.back().b, st);
     }
     // after the final stream sync of the sort (every event is complete)
@@ -328,6 +331,7 @@ struct Prof {
                 C->prof_ms[r.k] += ms;
                 C->prof_launch[r.k] += 1;
                 C->prof_bytes[r.k] += r.bytes;
+                C->prof_extra[r.k] += r.extra;
             }
         }
         recs.clear();
@@ -679,7 +683,9 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
                                 (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, (uint16_t*)C->ids.p, R.max_fanout,
                                 R.max_leaves, flags, nullptr, st));
-        prof.end((double)R.nkeys * 10.0);
+        // the method reads each key once; the u16 bucket id it writes for
+        // the scatter is the design's own traffic
+        prof.end((double)R.nkeys * 8.0, (double)R.nkeys * 2.0);
         prof.begin(2);
         HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, R.entries, (uint64_t*)C->scantmp.p,
                                 nullptr, st));
@@ -700,11 +706,13 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         prof.end(0.0);
         TRY(wait_published(C, st));
         if (prof.recs.size() > scatter_rec) {
-            // scatter: reads every key (and its bucket id) of a task that
-            // progressed, writes those not in all-equal buckets
+            // scatter: reads every key of a task that progressed and writes
+            // those not in all-equal buckets; the bucket id read beside each
+            // key is the design's own traffic
             const double moved = (double)(R.nkeys - (C->h_ctl->stall_keys - R.stall_keys));
             const double kept = moved - (double)(C->h_ctl->fillkeys - R.fillkeys);
-            prof.recs.back().bytes = 10.0 * moved + 8.0 * kept;
+            prof.recs.back().bytes = 8.0 * moved + 8.0 * kept;
+            prof.recs.back().extra = 2.0 * moved;
         }
         TRY(check_overflow(C));
     }
@@ -1493,6 +1501,8 @@ ls_status ls_last_profile(ls_ctx* C, double* out, size_t cap)
         out[3 * k] = C->prof_ms[k];
         out[3 * k + 1] = C->prof_launch[k];
         out[3 * k + 2] = C->prof_bytes[k];
+        if (cap >= 32)
+            out[24 + k] = C->prof_extra[k];
     }
     return LS_OK;
 }
@@ -1502,7 +1512,7 @@ ls_status ls_profile_reset(ls_ctx* C)
     if (!C)
         return LS_ERR_INVALID;
     for (int k = 0; k < 8; ++k)
-        C->prof_ms[k] = C->prof_launch[k] = C->prof_bytes[k] = 0;
+        C->prof_ms[k] = C->prof_launch[k] = C->prof_bytes[k] = C->prof_extra[k] = 0;
     return LS_OK;
 }
 
