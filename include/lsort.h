@@ -109,6 +109,31 @@ ls_status ls_reserve(ls_ctx* ctx, size_t n, const ls_params* p);
 ls_status ls_sort_f64(ls_ctx* ctx, double* d_keys, size_t n, ls_stream_t stream, const ls_params* p);
 ls_status ls_sort_u64(ls_ctx* ctx, uint64_t* d_keys, size_t n, ls_stream_t stream, const ls_params* p);
 
+/* Largest n ls_sort_noalloc takes. */
+#define LS_NOALLOC_MAX_KEYS (1u << 20)
+
+/* For callers that cannot allocate memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation, setups
+ * that reserve all other device memory): the same sort as ls_sort_f64 /
+ * ls_sort_u64 (dtype selects which), giving the same bits, but every device
+ * buffer it needs is cut from one static 128 MiB array per device that is
+ * part of the library's code object (loaded, and held until the process
+ * ends, on each device the library runs on; its address is looked up by
+ * ls_create).  The call allocates no device or pinned memory and grows no
+ * buffer of the context.
+ *  - n <= LS_NOALLOC_MAX_KEYS (1,048,576); a larger n is rejected with
+ *    LS_ERR_UNSUPPORTED before any work.  Parameters whose tables do not fit
+ *    the array for this n (a fanout of 4096 at the largest n, a tiny
+ *    base_threshold) are rejected the same way; the defaults always fit.
+ *  - LS_FLAG_PROFILE and LS_FLAG_GRAPH are rejected (LS_ERR_UNSUPPORTED).
+ *  - Synchronous: returns once the sort is complete.
+ *  - Every call on a device shares that device's array and leaves its
+ *    contents behind; the call clears what must start at zero.  Calls that
+ *    overlap on one device (other contexts, other threads) race on the array
+ *    and corrupt each other's results: serialise them. */
+ls_status ls_sort_noalloc(ls_ctx* ctx, ls_dtype dtype, void* d_keys, size_t n, ls_stream_t stream,
+                          const ls_params* p);
+
 /* Sort many independent arrays in one batched pipeline.  d_keys holds the
  * segments back to back; h_offsets (HOST memory, num_segments + 1 entries,
  * non-decreasing, h_offsets[0] = 0) gives each segment's key range.

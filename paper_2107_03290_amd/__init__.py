@@ -34,6 +34,8 @@ def FLAG_PROFILE_ONLY(k: int) -> int:
 
 KERNEL_CLASSES = ("train", "hist", "scan", "classify", "scatter", "base", "fill", "touchup")
 
+NOALLOC_MAX_KEYS = 1 << 20
+
 DEV_SEAM_REPAIRED = 0x1
 DEV_FALLBACK = 0x2
 DEV_DEEP = 0x4
@@ -45,7 +47,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime er
 # C-ABI entry points declared in include/lsort.h
 EXPORTS = (
     "ls_create", "ls_destroy", "ls_default_params", "ls_workspace_size", "ls_reserve",
-    "ls_sort_f64", "ls_sort_u64", "ls_sort_segments", "ls_sort_arrays", "ls_autotune", "ls_sync",
+    "ls_sort_f64", "ls_sort_u64", "ls_sort_noalloc", "ls_sort_segments", "ls_sort_arrays", "ls_autotune", "ls_sync",
     "ls_last_stats", "ls_last_profile", "ls_profile_reset", "ls_status_string", "ls_last_error",
     "ls_model_train", "ls_stage_hist",
     "ls_server_create", "ls_server_submit", "ls_server_wait", "ls_server_stats",
@@ -106,6 +108,7 @@ def lib() -> ctypes.CDLL:
             L.ls_reserve.argtypes = [vp, sz, P(Params)]
             L.ls_sort_f64.argtypes = [vp, vp, sz, vp, P(Params)]
             L.ls_sort_u64.argtypes = [vp, vp, sz, vp, P(Params)]
+            L.ls_sort_noalloc.argtypes = [vp, ctypes.c_int, vp, sz, vp, P(Params)]
             L.ls_sort_segments.argtypes = [vp, ctypes.c_int, vp, P(u64), sz, P(ctypes.c_uint8), vp, P(Params)]
             L.ls_sort_arrays.argtypes = [vp, P(Array), sz, vp, P(Params)]
             L.ls_autotune.argtypes = [vp, P(Array), sz, vp, P(Params), ctypes.c_uint32, P(Params),
@@ -198,6 +201,13 @@ class Sorter:
         code = _dtype_code(t)
         fn = lib().ls_sort_f64 if code == F64 else lib().ls_sort_u64
         self._check(fn(self._ctx, t.data_ptr(), t.numel(), _stream_handle(t), _pp(p)))
+
+    def sort_noalloc_(self, t, p: Params | None = None):
+        """The same sort out of the library's static per-device array, with no
+        allocation (at most NOALLOC_MAX_KEYS keys; synchronous)."""
+        _check_tensor(t)
+        self._check(lib().ls_sort_noalloc(self._ctx, _dtype_code(t), t.data_ptr(), t.numel(), _stream_handle(t),
+                                          _pp(p)))
         return t
 
     def sort_segments_(self, t, offsets: Sequence[int], dtypes: Sequence[int] | None = None,

@@ -12,6 +12,7 @@
 #include "lsort_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
@@ -122,6 +123,11 @@ struct ls_ctx {
     hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     std::vector<GraphEntry> graphs;
     std::vector<RoundsHint> hints;
+    // no-allocation sorts (ls_sort_noalloc): this device's static array, and
+    // whether the running sort works out of it (buffers never grow then)
+    void* na_base = nullptr;
+    size_t na_bytes = 0;
+    bool no_alloc = false;
 };
 
 namespace {
@@ -223,6 +229,9 @@ ls_status ensure(ls_ctx* C, DevBuf& b, size_t bytes, hipStream_t st, size_t keep
 {
     if (bytes <= b.cap && b.p)
         return LS_OK;
+    if (C->no_alloc)
+        return fail(C, LS_ERR_NOMEM, "no-allocation sort: a buffer needs " + std::to_string(bytes) +
+                                         " bytes, more than its share of the static array");
     size_t nb = std::max(bytes, b.cap + b.cap / 2);
     nb = std::max<size_t>(nb, 256);
     void* np = nullptr;
@@ -246,6 +255,9 @@ ls_status ensure_pinned(ls_ctx* C, PinBuf& b, size_t bytes, hipStream_t st)
 {
     if (bytes <= b.cap && b.p)
         return LS_OK;
+    if (C->no_alloc)
+        return fail(C, LS_ERR_NOMEM, "no-allocation sort: the round-0 lists need more pinned staging than the "
+                                     "context holds");
     HIPCHECK(C, hipStreamSynchronize(st));
     if (b.p)
         HIPCHECK(C, hipHostFree(b.p));
@@ -665,13 +677,18 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
                                                     R.nkeys / (kGroupClassCap[1] + 1) + 1};
         TRY(ensure(C, C->next, max_tasks * sizeof(Task), st));
         GroupLists gl;
+        // (a no-allocation sort keeps the lists it was given, sized for the
+        // whole sort; classify's capacity check guards them)
         for (uint32_t c = 0; c < kGroupClasses; ++c) {
-            TRY(ensure(C, C->groups[c], ((size_t)R.ngroups[c] + max_groups[c]) * sizeof(Group), st,
-                       (size_t)R.ngroups[c] * sizeof(Group)));
+            if (!C->no_alloc)
+                TRY(ensure(C, C->groups[c], ((size_t)R.ngroups[c] + max_groups[c]) * sizeof(Group), st,
+                           (size_t)R.ngroups[c] * sizeof(Group)));
             gl.g[c] = (Group*)C->groups[c].p;
             lp.cap_groups[c] = C->groups[c].cap / sizeof(Group);
         }
-        TRY(ensure(C, C->fills, ((size_t)R.nfill + max_fills) * sizeof(Fill), st, (size_t)R.nfill * sizeof(Fill)));
+        if (!C->no_alloc)
+            TRY(ensure(C, C->fills, ((size_t)R.nfill + max_fills) * sizeof(Fill), st,
+                       (size_t)R.nfill * sizeof(Fill)));
         lp.cap_fills = C->fills.cap / sizeof(Fill);
         // local models of this round's tasks (jobs written by the last layout)
         TRY(train(C, C->ljobs, R.njobs, R.blocks, R.samples, R.leafs, R.max_sample, lp.model_base, R.models, st,
@@ -726,7 +743,8 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
 ls_status launch_finish_lists(ls_ctx* C, const GroupLists& gl, const uint32_t* ngroups, const Fill* fills,
                               uint32_t nfill, const RoundCtl* gctl, hipStream_t st)
 {
-    const bool fork = !gctl && ((ngroups[1] && ngroups[2]) || ((ngroups[1] || ngroups[2]) && (ngroups[0] || nfill)));
+    const bool fork = !gctl && !C->no_alloc &&
+                      ((ngroups[1] && ngroups[2]) || ((ngroups[1] || ngroups[2]) && (ngroups[0] || nfill)));
     if (!fork) {
         for (uint32_t c = 0; c < kGroupClasses; ++c)
             HIPCHECK(C, launch_base(gl.g[c], ngroups[c], c, gctl, st));
@@ -1114,6 +1132,94 @@ ls_status run_graph(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const
     return LS_OK;
 }
 
+// ---------------------------------------------------- no-allocation sorts --
+//
+// ls_sort_noalloc runs the host-driven pipeline with every device buffer of
+// the context pointed into this device's static array instead of grown by
+// ensure().  The buffers are cut from bounds that hold for any input of n
+// keys: the per-round tables from the same bounds as a graph class of n keys
+// (one round's tasks, buckets, count-matrix entries, samples, leaves and
+// models), the lists that grow over the rounds from the fact that they
+// describe disjoint key ranges (a group holds at least one key, a group of
+// class c > 0 more than the previous class cap, an all-equal bucket at least
+// max(T/8, 2) keys and one piece per kFillPiece keys).  The layout and
+// classify kernels check every capacity on the device, so a bound that did
+// not hold would end the sort with an error, never write past a buffer.
+
+// The context's device buffers, in one list (save, carve, restore, free).
+constexpr size_t kCtxBufs = 24;
+std::array<DevBuf*, kCtxBufs> ctx_bufs(ls_ctx* C)
+{
+    return {&C->scratch, &C->tune, &C->ids, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst,
+            &C->tnf, &C->gjobs, &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
+            &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2]};
+}
+
+struct Carve {
+    DevBuf* b;
+    size_t bytes;
+};
+
+// Buffers of a no-allocation sort of n keys with parameters P, and the
+// total of their 256-byte aligned sizes.
+std::vector<Carve> noalloc_plan(ls_ctx* C, uint64_t n, const Params& P, size_t* total)
+{
+    const Caps K = graph_caps(n, 1, P);
+    const uint64_t fill_min = std::max<uint64_t>(P.base / 8, 2);
+    const uint64_t samples = std::max(K.gsamples, K.samples);
+    const uint64_t leafs = std::max(K.gleafs, K.leafs);
+    const uint64_t tasks = std::max(K.tasks0, K.tasks);
+    std::vector<Carve> v = {
+        {&C->scratch, n * 8},
+        {&C->ids, n * 2},
+        {&C->ctl, sizeof(RoundCtl)},
+        {&C->tasks, tasks * sizeof(Task)},
+        {&C->next, tasks * sizeof(Task)},
+        {&C->gjobs, K.tasks0 * sizeof(ModelJob)},
+        {&C->ljobs, tasks * sizeof(ModelJob)},
+        {&C->models, (K.gmodels + K.models) * sizeof(double)},
+        {&C->sample, samples * 8},
+        {&C->sample2, samples * 8},
+        {&C->tbest, leafs * 8},
+        {&C->tfirst, leafs * 8},
+        {&C->tnf, tasks * 16},
+        {&C->cnt, K.entries * 4},
+        {&C->pos, K.entries * 8},
+        {&C->scantmp, scan_tmp_entries(K.entries) * 8},
+        {&C->bstat, K.buckets * 16},
+        {&C->skip, K.buckets},
+        {&C->tflags, tasks * 4},
+        {&C->groups[0], (n + 1) * sizeof(Group)},
+        {&C->groups[1], (n / (kGroupClassCap[0] + 1) + 1) * sizeof(Group)},
+        {&C->groups[2], (n / (kGroupClassCap[1] + 1) + 1) * sizeof(Group)},
+        {&C->fills, (n / fill_min + n / kFillPiece + 2) * sizeof(Fill)},
+    };
+    size_t off = 0;
+    for (auto& c : v)
+        off += (std::max<size_t>(c.bytes, 8) + 255) & ~(size_t)255;
+    *total = off;
+    return v;
+}
+
+// Capacities of the carved buffers, for the device-side checks.
+LayoutParams noalloc_layout_params(ls_ctx* C, const Params& P, uint64_t model_base)
+{
+    LayoutParams lp = layout_params(P, model_base);
+    lp.cap_tasks = std::min({C->next.cap / sizeof(Task), C->tasks.cap / sizeof(Task), C->ljobs.cap / sizeof(ModelJob),
+                             C->tflags.cap / 4, C->tnf.cap / 16});
+    lp.cap_fills = C->fills.cap / sizeof(Fill);
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        lp.cap_groups[c] = C->groups[c].cap / sizeof(Group);
+    lp.cap_keys = std::min(C->ids.cap / 2, C->scratch.cap / 8);
+    lp.cap_buckets = std::min(C->bstat.cap / 16, C->skip.cap);
+    lp.cap_entries = std::min(C->cnt.cap / 4, C->pos.cap / 8);
+    lp.cap_samples = std::min(C->sample.cap, C->sample2.cap) / 8;
+    lp.cap_leafs = std::min(C->tbest.cap, C->tfirst.cap) / 8;
+    const uint64_t pool = C->models.cap / sizeof(double);
+    lp.cap_models = pool > model_base ? pool - model_base : 0;
+    return lp;
+}
+
 // The whole pipeline for a batch of arrays.  msd_only: partition on the
 // order-preserving bits alone (the touch-up repair path).
 ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P, bool msd_only)
@@ -1150,7 +1256,7 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
     if (!B.tr.jobs.empty())
         TRY(train(C, C->gjobs, (uint32_t)B.tr.jobs.size(), B.tr.blocks, B.tr.samples, B.tr.leaves,
                   B.tr.max_sample, 0, B.tr.models, st, &prof));
-    const LayoutParams lp = layout_params(P, global_models);
+    const LayoutParams lp = C->no_alloc ? noalloc_layout_params(C, P, global_models) : layout_params(P, global_models);
     if (!B.tasks.empty()) {
         LayoutParams lp0 = lp;
         lp0.host_flag = C->d_h_flag;
@@ -1237,6 +1343,18 @@ ls_status ls_create(ls_ctx** out, int device)
         return LS_ERR_NOMEM;
     }
     *C->h_flag = 0;
+    // the no-allocation sort's static array on this device (the device is
+    // current), and pinned staging for its round-0 lists
+    if (noalloc_setup(device, &C->na_base, &C->na_bytes) != hipSuccess ||
+        ensure_pinned(C, C->estage, 65536, nullptr) != LS_OK) {
+        (void)hipGetLastError();
+        (void)hipHostFree(C->h_ctl);
+        (void)hipHostFree(C->h_flag);
+        if (C->estage.p)
+            (void)hipHostFree(C->estage.p);
+        delete C;
+        return LS_ERR_HIP;
+    }
     *out = C;
     return LS_OK;
 }
@@ -1248,11 +1366,7 @@ ls_status ls_destroy(ls_ctx* C)
         return LS_ERR_INVALID;
     (void)hipSetDevice(C->device);
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&C->scratch, &C->tune, &C->ids, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst,
-                      &C->tnf, &C->gjobs,
-                      &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
-                      &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2]};
-    for (DevBuf* b : bufs)
+    for (DevBuf* b : ctx_bufs(C))
         if (b->p)
             (void)hipFree(b->p);
     PinBuf* pins[] = {&C->pin_jobs, &C->estage, &C->gstage};
@@ -1319,6 +1433,70 @@ ls_status ls_sort_u64(ls_ctx* C, uint64_t* d_keys, size_t n, ls_stream_t stream,
         return LS_ERR_INVALID;
     std::vector<Array> a{Array{d_keys, nullptr, n, LS_U64}};
     return sort_arrays(C, a, (hipStream_t)stream, p);
+}
+
+ls_status ls_sort_noalloc(ls_ctx* C, ls_dtype dtype, void* d_keys, size_t n, ls_stream_t stream,
+                          const ls_params* p)
+{
+    GateUse gate;
+    if (!C)
+        return LS_ERR_INVALID;
+    if (dtype != LS_F64 && dtype != LS_U64)
+        return fail(C, LS_ERR_INVALID, "unknown dtype");
+    if (n && !d_keys)
+        return fail(C, LS_ERR_INVALID, "null key pointer with n > 0");
+    if (((uintptr_t)d_keys) & 7u)
+        return fail(C, LS_ERR_INVALID, "key buffer must be 8-byte aligned");
+    if (n > LS_NOALLOC_MAX_KEYS)
+        return fail(C, LS_ERR_UNSUPPORTED, "ls_sort_noalloc sorts at most " + std::to_string(LS_NOALLOC_MAX_KEYS) +
+                                               " keys; got " + std::to_string(n));
+    Params P;
+    TRY(resolve(C, p, P));
+    if (P.flags & (LS_FLAG_PROFILE | LS_FLAG_GRAPH))
+        return fail(C, LS_ERR_UNSUPPORTED, "ls_sort_noalloc takes neither LS_FLAG_PROFILE nor LS_FLAG_GRAPH");
+    if (!C->na_base)
+        return fail(C, LS_ERR_HIP, "the no-allocation array of this device was not found");
+    size_t need = 0;
+    const std::vector<Carve> plan = noalloc_plan(C, n, P, &need);
+    if (need > C->na_bytes)
+        return fail(C, LS_ERR_UNSUPPORTED, "these parameters need " + std::to_string(need) +
+                                               " bytes of scratch for " + std::to_string(n) + " keys; the static array "
+                                               "holds " + std::to_string(C->na_bytes));
+    HIPCHECK(C, hipSetDevice(C->device));
+    C->dev_status = 0;
+    std::memset(C->stats, 0, sizeof C->stats);
+    if (n <= 1)
+        return LS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    // point every buffer of the context into the array; put them back after
+    std::array<DevBuf, kCtxBufs> saved;
+    const auto bufs = ctx_bufs(C);
+    for (size_t i = 0; i < kCtxBufs; ++i) {
+        saved[i] = *bufs[i];
+        *bufs[i] = DevBuf{};
+    }
+    unsigned char* base = (unsigned char*)C->na_base;
+    size_t off = 0;
+    for (const Carve& c : plan) {
+        const size_t sz = (std::max<size_t>(c.bytes, 8) + 255) & ~(size_t)255;
+        c.b->p = base + off;
+        c.b->cap = sz;
+        off += sz;
+    }
+    C->no_alloc = true;
+    std::vector<Array> a{Array{(uint64_t*)d_keys, nullptr, n, (uint32_t)dtype}};
+    // the training tables must start at zero (the array keeps whatever the
+    // last call on this device left there)
+    ls_status rc = LS_OK;
+    for (DevBuf* t : {&C->tbest, &C->tfirst, &C->tnf})
+        if (rc == LS_OK && launch_zero(t->p, t->cap, st) != hipSuccess)
+            rc = fail(C, LS_ERR_HIP, "clearing the training tables failed");
+    if (rc == LS_OK)
+        rc = run_pipeline(C, a, st, P, false);
+    C->no_alloc = false;
+    for (size_t i = 0; i < kCtxBufs; ++i)
+        *bufs[i] = saved[i];
+    return rc;
 }
 
 ls_status ls_sort_segments(ls_ctx* C, ls_dtype dtype, void* d_keys, const uint64_t* h_offsets,

@@ -20,6 +20,8 @@ constexpr uint32_t kLocalMinSample = 1024; // smallest sample of a local model
 constexpr uint32_t kSampleBlock = 4096;    // sample keys per training block (one LDS-sorted run)
 constexpr uint32_t kGroupClasses = 3;      // base-case size classes: <= 1024, 4096, 8192 keys
 constexpr uint32_t kGroupClassCap[kGroupClasses] = {1024, 4096, 8192};
+// Static device array of the no-allocation sort, per device.
+constexpr size_t kNoAllocBytes = (size_t)128 << 20;
 
 // How a task maps a key to a bucket.
 enum TaskKind : uint32_t {
@@ -288,6 +290,11 @@ hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_c
 // One size class (cls) of base-case groups.
 hipError_t launch_base(const Group* groups, uint32_t ngroups, uint32_t cls, const RoundCtl* gctl, hipStream_t st);
 hipError_t launch_fill(const Fill* d_fills, uint32_t nfill, const RoundCtl* gctl, hipStream_t st);
+// No-allocation sort: device address and size of this device's static
+// array (looked up once per device; the device must be current).
+hipError_t noalloc_setup(int device, void** out, size_t* bytes);
+// Clear bytes / 8 words at p with a kernel on st.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_touchup(GroupLists groups, const uint32_t* ngroups, const Fill* d_fills, uint32_t nfill,
                           int full, RoundCtl* d_ctl, bool graph, hipStream_t st);
 
