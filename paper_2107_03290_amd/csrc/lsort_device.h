@@ -195,6 +195,19 @@ __device__ __forceinline__ uint32_t msd_bucket(uint64_t raw, uint32_t shift, uin
     return (uint32_t)((to_ord(raw, DT) >> shift) & (uint64_t)(fanout - 1u));
 }
 
+// ------------------------------------------------------ workgroup order --
+
+// Workgroups of a launch are handed to the eight XCDs in turn (workgroup b
+// runs on XCD b mod 8), and each XCD has its own L2.  xcd_order maps b to a
+// work index so that every XCD gets one contiguous range of work items:
+// neighbouring items, whose outputs meet in shared cache lines, then run on
+// the same XCD.  A bijection of [0, grid).
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t grid)
+{
+    const uint32_t x = b & 7u, j = b >> 3, q = grid >> 3, r = grid & 7u;
+    return x * q + (x < r ? x : r) + j;
+}
+
 // ------------------------------------------------------- LDS bitonic sort --
 
 // Ascending bitonic network over N = 2^logN (16 <= N <= 16 * NT) words in
@@ -204,7 +217,13 @@ __device__ __forceinline__ uint32_t msd_bucket(uint64_t raw, uint32_t shift, uin
 // each LDS round trip runs four stages in registers; a phase of the network
 // needs ceil(p/4) round trips.  All NT threads call it; the words must be in
 // LDS and synchronised on entry, and are sorted and synchronised on exit.
+// PAD = false: the words sit at plain indices (more bank conflicts).
 __host__ __device__ __forceinline__ uint32_t base_pad(uint32_t i) { return i + (i >> 4); }
+
+// LDS word of element i: padded (one spare word per 16 against bank
+// conflicts) or plain.
+template <bool PAD>
+__device__ __forceinline__ uint32_t lds_at(uint32_t i) { return PAD ? base_pad(i) : i; }
 
 // element index of register m of thread t, the 4 register bits at [lo, lo+4)
 __device__ __forceinline__ uint32_t base_idx(uint32_t t, uint32_t lo, uint32_t m)
@@ -236,7 +255,7 @@ __device__ __forceinline__ void reg_stages(uint64_t (&r)[16], uint32_t top, bool
     }
 }
 
-template <uint32_t NT>
+template <uint32_t NT, bool PAD = true>
 __device__ void lds_bitonic(uint64_t* s, uint32_t logN)
 {
     const uint32_t t = threadIdx.x;
@@ -246,7 +265,7 @@ __device__ void lds_bitonic(uint64_t* s, uint32_t logN)
     if (act) {
 #pragma unroll
         for (int m = 0; m < 16; ++m)
-            r[m] = s[base_pad(16 * t + m)];
+            r[m] = s[lds_at<PAD>(16 * t + m)];
 #pragma unroll
         for (int p = 1; p <= 4; ++p) {
 #pragma unroll
@@ -263,7 +282,7 @@ __device__ void lds_bitonic(uint64_t* s, uint32_t logN)
         }
 #pragma unroll
         for (int m = 0; m < 16; ++m)
-            s[base_pad(16 * t + m)] = r[m];
+            s[lds_at<PAD>(16 * t + m)] = r[m];
     }
     __syncthreads();
     // phases 5..logN: stages on bits p-1 .. 0 in windows of four bits
@@ -276,11 +295,11 @@ __device__ void lds_bitonic(uint64_t* s, uint32_t logN)
                 const bool up = p == logN || ((i0 >> p) & 1u) == 0;
 #pragma unroll
                 for (int m = 0; m < 16; ++m)
-                    r[m] = s[base_pad(base_idx(t, lo, (uint32_t)m))];
+                    r[m] = s[lds_at<PAD>(base_idx(t, lo, (uint32_t)m))];
                 reg_stages(r, (uint32_t)bit - lo, up);
 #pragma unroll
                 for (int m = 0; m < 16; ++m)
-                    s[base_pad(base_idx(t, lo, (uint32_t)m))] = r[m];
+                    s[lds_at<PAD>(base_idx(t, lo, (uint32_t)m))] = r[m];
             }
             __syncthreads();
             bit = (int32_t)lo - 1;
