@@ -90,14 +90,12 @@ def cpu_library_sort(a: np.ndarray, sample: int):
             "sample": "first %d keys, %.1f s" % (sample, dt)}
 
 
-def roofline(prof: dict, wname: str, overhead: dict | None = None) -> dict:
+def roofline(prof: dict, wname: str) -> dict:
     """Roofline entry of the dominant kernel class: algorithmic bytes per
     launch over the average launch time (HIP events on the sort's stream).
     Algorithmic bytes are the method's: the histogram reads 8 B per key, the
     scatter reads 8 B per key of a progressing range and writes 8 B per key
-    outside all-equal buckets, the base case reads and writes 8 B per key.
-    The design's own extra traffic (2-byte bucket ids) is reported beside
-    it, not in it."""
+    outside all-equal buckets, the base case reads and writes 8 B per key."""
     dom = max(("hist", "scatter", "base", "fill", "train"), key=lambda k: prof[k][0])
     ms, launches, byt = prof[dom]
     achieved = (byt / launches) / ((ms / launches) / 1e3) / 1e9 if launches else 0.0
@@ -110,7 +108,6 @@ def roofline(prof: dict, wname: str, overhead: dict | None = None) -> dict:
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "alg_bytes_per_launch": byt / launches if launches else 0.0,
-            "design_overhead_bytes_per_launch": (overhead or {}).get(dom, 0.0) / launches if launches else 0.0,
             "avg_launch_ms": ms / launches if launches else 0.0}
 
 
@@ -214,7 +211,7 @@ def bench_segments(args, torch, ls):
                   "calls": int(off.size - 1), "params": "defaults"},
         "batched_over_plain": ms_p / ms,
         "identical_to_plain": same,
-        "roofline": roofline(prof, "segments_%d_f64" % (off.size - 1), S.profile_overhead()),
+        "roofline": roofline(prof, "segments_%d_f64" % (off.size - 1)),
         "kernel_ms_per_step": breakdown,
         "kernel_ms_source": "%d untimed steps after the warm-up with every kernel class timed; the timed "
                             "steps time the dominant class (%s) only" % (PROFILED_STEPS, dom),
@@ -562,7 +559,7 @@ def main():
         "config": {"workload": wname, "n": n, "fanout": p.fanout, "leaves": p.leaves,
                    "tile": p.tile or "auto (4096; 8192 in rounds of >= 2^25 keys)",
                    "base_threshold": p.base_threshold, "sample_rate": p.sample_rate, "sample_cap": p.sample_cap},
-        "roofline": roofline(prof, wname, S.profile_overhead()),
+        "roofline": roofline(prof, wname),
         "kernel_ms_per_step": breakdown,
         "kernel_GBps": gbps,
         "kernel_ms_source": "%d untimed steps after the warm-up with every kernel class timed; the timed "

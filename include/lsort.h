@@ -196,9 +196,8 @@ ls_status ls_last_stats(ls_ctx* ctx, uint64_t* out8);
  * launches, [3*k + 2] algorithmic bytes (keys read + written as the method
  * requires: the histogram reads each key of a round once, the scatter reads
  * each key of a progressing range and writes each one outside all-equal
- * buckets).  With cap >= 32, out[24 + k] receives the bytes the design adds
- * beyond those (the 2-byte bucket id the histogram writes and the scatter
- * reads per key).  Classes k: 0 train, 1 histogram, 2 scan, 3 classify,
+ * buckets; both evaluate each key's bucket from the model, nothing is
+ * stored in between).  Classes k: 0 train, 1 histogram, 2 scan, 3 classify,
  * 4 scatter, 5 base case, 6 fill, 7 touch-up.  cap >= 24. */
 ls_status ls_last_profile(ls_ctx* ctx, double* out, size_t cap);
 ls_status ls_profile_reset(ls_ctx* ctx);

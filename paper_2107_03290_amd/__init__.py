@@ -279,13 +279,6 @@ class Sorter:
         self._check(lib().ls_last_profile(self._ctx, a, 24))
         return {k: (a[3 * i], int(a[3 * i + 1]), a[3 * i + 2]) for i, k in enumerate(KERNEL_CLASSES)}
 
-    def profile_overhead(self) -> dict:
-        """{class: bytes} the design moved beyond the method's algorithmic
-        bytes (the 2-byte bucket ids), for the same sorts as profile()."""
-        a = (ctypes.c_double * 32)()
-        self._check(lib().ls_last_profile(self._ctx, a, 32))
-        return {k: a[24 + i] for i, k in enumerate(KERNEL_CLASSES)}
-
     def profile_reset(self):
         self._check(lib().ls_profile_reset(self._ctx))
 

@@ -96,7 +96,7 @@ uint32_t group_class(uint32_t n)
 struct ls_ctx {
     int device = 0;
     std::string err;
-    DevBuf scratch, tune, ids, models, sample, sample2, tbest, tfirst, tnf, gjobs, ljobs, tasks, next, cnt, pos, scantmp,
+    DevBuf scratch, tune, models, sample, sample2, tbest, tfirst, tnf, gjobs, ljobs, tasks, next, cnt, pos, scantmp,
         bstat,
         skip, tflags, fills, ctl;
     DevBuf groups[kGroupClasses];
@@ -111,7 +111,6 @@ struct ls_ctx {
     size_t lds_limit = 65536;
     // LS_FLAG_PROFILE: event pairs around each kernel class
     double prof_ms[8] = {0}, prof_launch[8] = {0}, prof_bytes[8] = {0};
-    double prof_extra[8] = {0};   // bytes the design moves beyond the method's (the u16 bucket ids)
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     // graph mode
@@ -299,7 +298,6 @@ struct Prof {
         int k;
         hipEvent_t a, b;
         double bytes;
-        double extra;
     };
     std::vector<Rec> recs;
     int only = -1;        // time only this class (LS_FLAG_PROFILE_ONLY), -1: all
@@ -319,19 +317,18 @@ struct Prof {
         open = false;
         if (!on || (only >= 0 && k != only))
             return;
-        Rec r{k, ev(), ev(), 0.0, 0.0};
+        Rec r{k, ev(), ev(), 0.0};
         if (r.a && r.b && hipEventRecord(r.a, st) == hipSuccess) {
             recs.push_back(r);
             open = true;
         }
     }
-    void end(double bytes, double extra = 0.0)
+    void end(double bytes)
     {
         if (!open)
             return;
         open = false;
         recs.back().bytes = bytes;
-        recs.back().extra = extra;
         (void)hipEventRecord(recs.back().b, st);
     }
     // after the final stream sync of the sort (every event is complete)
@@ -343,7 +340,6 @@ struct Prof {
                 C->prof_ms[r.k] += ms;
                 C->prof_launch[r.k] += 1;
                 C->prof_bytes[r.k] += r.bytes;
-                C->prof_extra[r.k] += r.extra;
             }
         }
         recs.clear();
@@ -387,14 +383,19 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
         return fail(C, LS_ERR_INVALID, "base_threshold must be in [2, 4096]");
     if (!(P.rate > 0.0) || P.rate > 1.0)
         return fail(C, LS_ERR_INVALID, "sample_rate must be in (0, 1]");
-    size_t scatter_lds = scatter_lds_bytes(P.tile, P.fanout) + 128;
-    size_t hist_lds = (((size_t)P.fanout * 20 + 15) & ~(size_t)15) + model_lds_bytes(P.leaves) + 64;
-    if (scatter_lds > C->lds_limit || hist_lds > C->lds_limit)
+    // the scatter holds the staged tile, per-bucket tables and the model
+    const size_t model_lds = model_lds_bytes(P.leaves);
+    auto scatter_lds = [&](uint32_t tile) { return scatter_lds_bytes(tile, P.fanout) + model_lds + 128; };
+    if (P.tile_wide)   // automatic tile: the largest of 4096, 2048, 1024 that fits
+        while (P.tile > 1024 && scatter_lds(P.tile) > C->lds_limit)
+            P.tile /= 2;
+    size_t hist_lds = (((size_t)P.fanout * 20 + 15) & ~(size_t)15) + model_lds + 64;
+    if (scatter_lds(P.tile) > C->lds_limit || hist_lds > C->lds_limit)
         return fail(C, LS_ERR_UNSUPPORTED, "tile/fanout/leaves exceed the LDS of one workgroup");
     // automatic tile: the wide tile is taken only by rounds whose fanouts fit
     P.wide_max_fanout = 0;
     if (P.tile_wide) {
-        const size_t fixed = scatter_lds_bytes(P.tile_wide, 0) + 128 + 16;
+        const size_t fixed = scatter_lds_bytes(P.tile_wide, 0) + model_lds + 128 + 16;
         P.wide_max_fanout = C->lds_limit > fixed ? (uint32_t)std::min<size_t>((C->lds_limit - fixed) / 24, kMaxFanout)
                                                  : 0u;
         if (P.wide_max_fanout < 2)
@@ -657,7 +658,6 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         TRY(ensure(C, C->pos, R.entries * 8, st));
         TRY(ensure(C, C->scantmp, scan_tmp_entries(R.entries) * 8, st));
         TRY(ensure(C, C->bstat, (uint64_t)R.buckets * 16, st));
-        TRY(ensure(C, C->ids, R.nkeys * 2, st));
         TRY(ensure(C, C->skip, R.buckets, st));
         TRY(ensure(C, C->tflags, (size_t)nt * 4, st));
         // Output lists, sized by what classify can emit: a next-round task
@@ -698,11 +698,10 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, R.buckets, (RoundCtl*)C->ctl.p, false, st));
         prof.begin(1);
         HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
-                                (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, (uint16_t*)C->ids.p, R.max_fanout,
-                                R.max_leaves, flags, nullptr, st));
-        // the method reads each key once; the u16 bucket id it writes for
-        // the scatter is the design's own traffic
-        prof.end((double)R.nkeys * 8.0, (double)R.nkeys * 2.0);
+                                (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, R.max_fanout, R.max_leaves, flags,
+                                nullptr, st));
+        // the method reads each key once
+        prof.end((double)R.nkeys * 8.0);
         prof.begin(2);
         HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, R.entries, (uint64_t*)C->scantmp.p,
                                 nullptr, st));
@@ -717,19 +716,18 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         prof.end((double)R.buckets * 32.0);
         const size_t scatter_rec = prof.recs.size();
         prof.begin(4);
-        HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const uint16_t*)C->ids.p,
+        HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
                                    (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
-                                   (const uint32_t*)C->tflags.p, R.tile, R.max_fanout, nullptr, st));
+                                   (const uint32_t*)C->tflags.p, R.tile, R.max_fanout, R.max_leaves, flags, nullptr,
+                                   st));
         prof.end(0.0);
         TRY(wait_published(C, st));
         if (prof.recs.size() > scatter_rec) {
             // scatter: reads every key of a task that progressed and writes
-            // those not in all-equal buckets; the bucket id read beside each
-            // key is the design's own traffic
+            // those not in all-equal buckets
             const double moved = (double)(R.nkeys - (C->h_ctl->stall_keys - R.stall_keys));
             const double kept = moved - (double)(C->h_ctl->fillkeys - R.fillkeys);
             prof.recs.back().bytes = 8.0 * moved + 8.0 * kept;
-            prof.recs.back().extra = 2.0 * moved;
         }
         TRY(check_overflow(C));
     }
@@ -949,7 +947,6 @@ ls_status size_for_graph(ls_ctx* C, const Caps& K, hipStream_t st)
     TRY(ensure(C, C->pos, K.entries * 8, st));
     TRY(ensure(C, C->scantmp, scan_tmp_entries(K.entries) * 8, st));
     TRY(ensure(C, C->bstat, K.buckets * 16, st));
-    TRY(ensure(C, C->ids, K.keys * 2, st));
     TRY(ensure(C, C->skip, K.buckets, st));
     TRY(ensure(C, C->tflags, K.tasks * 4, st));
     for (uint32_t c = 0; c < kGroupClasses; ++c)
@@ -1012,16 +1009,16 @@ ls_status record_graph(ls_ctx* C, const Caps& K, const Params& P, uint32_t round
                                      K.samples, K.max_sample, sample, sample2, tbest, tfirst, tnf, models, live,
                                      cs));
         HIPCHECK(C, launch_hist(in, nt, (uint32_t)K.chunks, 0, models, (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p,
-                                (uint16_t*)C->ids.p, P.fanout, P.leaves, flags, live, cs));
+                                P.fanout, P.leaves, flags, live, cs));
         HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, K.entries, (uint64_t*)C->scantmp.p,
                                 live, cs));
         HIPCHECK(C, launch_classify(in, nt, (const uint64_t*)C->pos.p, (const uint64_t*)C->bstat.p, P.base,
                                     P.fanout, out, gl, (Fill*)C->fills.p, (uint8_t*)C->skip.p,
                                     (uint32_t*)C->tflags.p, ctl, P.fanout, (ModelJob*)C->ljobs.p, lp, C->d_h_ctl,
                                     live, cs));
-        HIPCHECK(C, launch_scatter(in, nt, (uint32_t)K.chunks, 0, (const uint16_t*)C->ids.p,
-                                   (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
-                                   (const uint32_t*)C->tflags.p, P.tile, P.fanout, live, cs));
+        HIPCHECK(C, launch_scatter(in, nt, (uint32_t)K.chunks, 0, models, (const uint64_t*)C->pos.p,
+                                   (const uint8_t*)C->skip.p, (const uint32_t*)C->tflags.p, P.tile, P.fanout, P.leaves,
+                                   flags, live, cs));
     }
     uint32_t gmax[kGroupClasses];
     for (uint32_t c = 0; c < kGroupClasses; ++c)
@@ -1147,10 +1144,10 @@ ls_status run_graph(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const
 // not hold would end the sort with an error, never write past a buffer.
 
 // The context's device buffers, in one list (save, carve, restore, free).
-constexpr size_t kCtxBufs = 24;
+constexpr size_t kCtxBufs = 23;
 std::array<DevBuf*, kCtxBufs> ctx_bufs(ls_ctx* C)
 {
-    return {&C->scratch, &C->tune, &C->ids, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst,
+    return {&C->scratch, &C->tune, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst,
             &C->tnf, &C->gjobs, &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
             &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2]};
 }
@@ -1171,7 +1168,6 @@ std::vector<Carve> noalloc_plan(ls_ctx* C, uint64_t n, const Params& P, size_t* 
     const uint64_t tasks = std::max(K.tasks0, K.tasks);
     std::vector<Carve> v = {
         {&C->scratch, n * 8},
-        {&C->ids, n * 2},
         {&C->ctl, sizeof(RoundCtl)},
         {&C->tasks, tasks * sizeof(Task)},
         {&C->next, tasks * sizeof(Task)},
@@ -1210,7 +1206,7 @@ LayoutParams noalloc_layout_params(ls_ctx* C, const Params& P, uint64_t model_ba
     lp.cap_fills = C->fills.cap / sizeof(Fill);
     for (uint32_t c = 0; c < kGroupClasses; ++c)
         lp.cap_groups[c] = C->groups[c].cap / sizeof(Group);
-    lp.cap_keys = std::min(C->ids.cap / 2, C->scratch.cap / 8);
+    lp.cap_keys = C->scratch.cap / 8;
     lp.cap_buckets = std::min(C->bstat.cap / 16, C->skip.cap);
     lp.cap_entries = std::min(C->cnt.cap / 4, C->pos.cap / 8);
     lp.cap_samples = std::min(C->sample.cap, C->sample2.cap) / 8;
@@ -1403,8 +1399,8 @@ ls_status ls_workspace_size(ls_ctx* C, ls_dtype dtype, size_t n, const ls_params
     size_t chunks = kTargetChunks + 64;
     size_t tables = (size_t)P.fanout * chunks * 12 + (size_t)P.fanout * 64 + model_doubles(P.leaves) * 8 * 4;
     size_t lists = (n / 2 + P.fanout) * (sizeof(Group) + sizeof(Fill)) / 8;
-    // scratch keys, bucket ids, round tables, output lists, training sample
-    *bytes = n * 8 + n * 2 + tables + lists + (2 * std::min<size_t>(n / 50 + 4096, kDefaultSampleCap + 4096)) * 8;
+    // scratch keys, round tables, output lists, training sample
+    *bytes = n * 8 + tables + lists + (2 * std::min<size_t>(n / 50 + 4096, kDefaultSampleCap + 4096)) * 8;
     return LS_OK;
 }
 
@@ -1679,8 +1675,6 @@ ls_status ls_last_profile(ls_ctx* C, double* out, size_t cap)
         out[3 * k] = C->prof_ms[k];
         out[3 * k + 1] = C->prof_launch[k];
         out[3 * k + 2] = C->prof_bytes[k];
-        if (cap >= 32)
-            out[24 + k] = C->prof_extra[k];
     }
     return LS_OK;
 }
@@ -1690,7 +1684,7 @@ ls_status ls_profile_reset(ls_ctx* C)
     if (!C)
         return LS_ERR_INVALID;
     for (int k = 0; k < 8; ++k)
-        C->prof_ms[k] = C->prof_launch[k] = C->prof_bytes[k] = C->prof_extra[k] = 0;
+        C->prof_ms[k] = C->prof_launch[k] = C->prof_bytes[k] = 0;
     return LS_OK;
 }
 
@@ -1806,10 +1800,8 @@ ls_status ls_stage_hist(ls_ctx* C, ls_dtype dtype, const void* d_keys, size_t n,
     TRY(ensure(C, C->bstat, (size_t)fanout * 16, st));
     HIPCHECK(C, hipMemcpy(C->tasks.p, &t, sizeof(Task), hipMemcpyHostToDevice));
     HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, fanout, (RoundCtl*)C->ctl.p, false, st));
-    TRY(ensure(C, C->ids, n * 2, st));
     HIPCHECK(C, launch_hist((const Task*)C->tasks.p, 1, t.nchunks, chunk, (const double*)C->models.p,
-                            (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, (uint16_t*)C->ids.p, fanout, leaves, 0,
-                            nullptr, st));
+                            (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, fanout, leaves, 0, nullptr, st));
     HIPCHECK(C, hipDeviceSynchronize());
     std::vector<uint32_t> cnt((size_t)fanout * t.nchunks);
     std::vector<uint64_t> bs((size_t)fanout * 2);

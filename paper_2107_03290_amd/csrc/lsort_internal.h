@@ -189,9 +189,9 @@ __host__ __device__ inline size_t model_lds_bytes(uint32_t L)
 // large still has thousands of chunks.
 constexpr uint64_t kWideTileKeys = 1ull << 25;
 
-// LDS bytes of the scatter: the staged tile (8 B keys + 2 B ids) and, per
-// bucket, the cursor and the tile's write base (8 B each), tile count and
-// tile start (4 B each).
+// LDS bytes of the scatter without its model: the staged tile (8 B keys + 2 B
+// bucket numbers) and, per bucket, the cursor and the tile's write base (8 B
+// each), tile count and tile start (4 B each).
 __host__ __device__ inline size_t scatter_lds_bytes(uint32_t tile, uint32_t fanout)
 {
     return ((size_t)tile * 10 + (size_t)fanout * 24 + 15) & ~(size_t)15;
@@ -256,7 +256,7 @@ hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_b
 // clear ctl->buckets entries (nbuckets is then the grid's upper bound).
 hipError_t launch_round_init(uint64_t* d_bstat, uint64_t nbuckets, RoundCtl* d_ctl, bool snapshot, hipStream_t st);
 hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
-                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint16_t* d_ids,
+                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat,
                        uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, const LiveCounts* live,
                        hipStream_t st);
 hipError_t launch_scan(const uint32_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_tmp, const LiveCounts* live,
@@ -276,12 +276,12 @@ hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t*
 // to host_ctl.
 hipError_t launch_layout(Task* d_next, ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* d_ctl,
                          RoundCtl* host_ctl, hipStream_t st);
-// d_ids: the bucket of every key of the round, written by the histogram
-// (indexed by the task's cnt_base + position in the task).
+// The scatter evaluates each key's bucket again from the task's model (the
+// same arithmetic as the histogram).
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
-                          const uint16_t* d_ids, const uint64_t* d_pos, const uint8_t* d_skip,
-                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, const LiveCounts* live,
-                          hipStream_t st);
+                          const double* d_models, const uint64_t* d_pos, const uint8_t* d_skip,
+                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, uint32_t max_leaves,
+                          uint32_t flags, const LiveCounts* live, hipStream_t st);
 // Finishing kernels.  gctl (graph mode, may be null): ngroups / nfill are
 // upper bounds, the real counts are read from gctl, and nothing is done
 // while gctl->ntasks says partition rounds are still pending or after an

@@ -143,7 +143,7 @@ __device__ __forceinline__ void wave_count(uint32_t* h, uint32_t b, bool valid)
 template <uint32_t DT, bool MSD>
 __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, gptr<const uint64_t> src, uint32_t cnt,
                                           uint32_t* h, unsigned long long* mn, unsigned long long* mx,
-                                          uint16_t* ids, uint32_t flags)
+                                          uint32_t flags)
 {
     constexpr uint32_t STEP = kHistThreads * kHistUnroll;
     const double scale = T.scale;
@@ -176,7 +176,6 @@ __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, gptr<c
                                    : model_bucket<DT>(M, raw[u], scale, offset, fanout, flags);
             wave_count(h, b, valid);
             if (valid) {
-                ids[i] = (uint16_t)b;
                 // Only a new extreme needs an atomic: min only falls and max
                 // only rises, so a stale read can cause an extra atomic but
                 // never a missed one.
@@ -192,7 +191,7 @@ __device__ __forceinline__ void hist_body(const Task& T, const SModel& M, gptr<c
 
 __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32_t ntasks, uint64_t chunk,
                                                        const double* models, uint32_t* cnt, uint64_t* bstat,
-                                                       uint16_t* ids, uint32_t flags, const LiveCounts* live)
+                                                       uint32_t flags, const LiveCounts* live)
 {
     if (live) {
         if (blockIdx.x >= live->chunks)
@@ -225,13 +224,12 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32
     const uint64_t lo = (uint64_t)lc * chunk;
     const uint32_t n = (uint32_t)(min(T.n, lo + chunk) - lo);
     const gptr<const uint64_t> src = as_global<const uint64_t>((T.src ? T.scratch : T.keys) + T.start + lo);
-    uint16_t* cid = ids + T.cnt_base + lo;
     if (T.dtype == kF64) {
-        if (msd) hist_body<kF64, true>(T, M, src, n, h, mn, mx, cid, flags);
-        else hist_body<kF64, false>(T, M, src, n, h, mn, mx, cid, flags);
+        if (msd) hist_body<kF64, true>(T, M, src, n, h, mn, mx, flags);
+        else hist_body<kF64, false>(T, M, src, n, h, mn, mx, flags);
     } else {
-        if (msd) hist_body<kU64, true>(T, M, src, n, h, mn, mx, cid, flags);
-        else hist_body<kU64, false>(T, M, src, n, h, mn, mx, cid, flags);
+        if (msd) hist_body<kU64, true>(T, M, src, n, h, mn, mx, flags);
+        else hist_body<kU64, false>(T, M, src, n, h, mn, mx, flags);
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
@@ -244,15 +242,15 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const Task* tasks, uint32
 }
 
 hipError_t launch_hist(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
-                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat, uint16_t* d_ids,
+                       const double* d_models, uint32_t* d_cnt, uint64_t* d_bstat,
                        uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, const LiveCounts* live,
                        hipStream_t st)
 {
     if (!total_chunks)
         return hipSuccess;
     size_t smem = (((size_t)max_fanout * 20 + 15) & ~(size_t)15) + model_lds_bytes(max_leaves);
-    k_hist<<<total_chunks, kHistThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_cnt, d_bstat, d_ids,
-                                                     flags, live);
+    k_hist<<<total_chunks, kHistThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_cnt, d_bstat, flags,
+                                                     live);
     return hipGetLastError();
 }
 
@@ -763,14 +761,15 @@ hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t*
 constexpr uint32_t kScatterThreads = 1024;
 
 // Scatter: stage one tile in LDS ordered by bucket, then write each bucket's
-// run at its cursor so consecutive lanes write consecutive addresses.  Bucket
-// ids come from the histogram pass (one u16 per key), so no model is
-// evaluated here.  The next tile's keys and ids are loaded while the current
-// one is ranked and written.
+// run at its cursor so consecutive lanes write consecutive addresses.  Each
+// key's bucket is computed again from the model (as in the histogram, with
+// the same arithmetic, so the same bucket): nothing is stored between the
+// two passes.  The next tile's keys are loaded while the current one is
+// ranked and written.
 //
 // LDS: the staged tile (8 B keys), then per bucket the cursor and the tile's
 // write base (8 B each), the tile count and tile start (4 B each), then the
-// staged ids (2 B per key).
+// staged bucket numbers (2 B per key), then the model.
 struct ScatterLds {
     uint64_t* stage;
     uint64_t* cur;
@@ -778,6 +777,7 @@ struct ScatterLds {
     uint32_t* tcnt;
     uint32_t* tstart;
     uint16_t* sb;
+    void* model;
 };
 
 __device__ __forceinline__ ScatterLds scatter_lds(unsigned char* smem, uint32_t tile, uint32_t f)
@@ -789,6 +789,7 @@ __device__ __forceinline__ ScatterLds scatter_lds(unsigned char* smem, uint32_t 
     L.tcnt = reinterpret_cast<uint32_t*>(L.wbase + f);
     L.tstart = L.tcnt + f;
     L.sb = reinterpret_cast<uint16_t*>(L.tstart + f);
+    L.model = smem + scatter_lds_bytes(tile, f);
     return L;
 }
 
@@ -798,52 +799,50 @@ __device__ __forceinline__ ScatterLds scatter_lds(unsigned char* smem, uint32_t 
 // write loop needs none behind it: the next tile's ranking touches only the
 // counts and the cursors' skip bits, and everything the write loop reads is
 // rewritten only after the next tile's first barrier.
-template <uint32_t KPT>
-__device__ __forceinline__ void scatter_body(const Task& T, gptr<const uint64_t> src, const uint16_t* ids,
+template <uint32_t KPT, uint32_t DT, bool MSD>
+__device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, gptr<const uint64_t> src,
                                              gptr<uint64_t> dst, uint32_t n, const ScatterLds& L,
-                                             uint32_t* wsum)
+                                             uint32_t* wsum, uint32_t flags)
 {
     constexpr uint32_t NT = kScatterThreads;
     constexpr uint32_t TILE = KPT * NT;
     const uint32_t f = T.fanout;
+    const double scale = T.scale;
+    const int32_t offset = (int32_t)T.offset;
+    const uint32_t shift = T.shift;
     // buckets of this thread in the tile scan
     const uint32_t per = (f + NT - 1) / NT;
     const uint32_t blo = min(f, threadIdx.x * per), bhi = min(f, blo + per);
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     uint64_t nxt[KPT];
-    uint32_t nid[KPT];   // widened: packing two ids per register would wait for the loads
 #pragma unroll
     for (uint32_t u = 0; u < KPT; ++u) {
         const uint32_t i = u * NT + threadIdx.x;
         nxt[u] = i < n ? src[i] : 0;
-        nid[u] = i < n ? ids[i] : 0;
     }
     for (uint32_t base = 0; base < n; base += TILE) {
         uint64_t raw[KPT];
         uint32_t bk[KPT];
         uint32_t rk[KPT];
-        uint32_t id[KPT];
 #pragma unroll
-        for (uint32_t u = 0; u < KPT; ++u) {
+        for (uint32_t u = 0; u < KPT; ++u)
             raw[u] = nxt[u];
-            id[u] = nid[u];
-        }
         if (base + TILE < n) {
 #pragma unroll
             for (uint32_t u = 0; u < KPT; ++u) {
                 const uint32_t i = base + TILE + u * NT + threadIdx.x;
                 nxt[u] = i < n ? src[i] : 0;
-                nid[u] = i < n ? ids[i] : 0;
             }
         }
-        // rank each key among the tile's keys of its bucket
+        // bucket of each key, and its rank among the tile's keys of that bucket
 #pragma unroll
         for (uint32_t u = 0; u < KPT; ++u) {
             const uint32_t i = base + u * NT + threadIdx.x;
             bk[u] = ~0u;
             rk[u] = 0;
             if (i < n) {
-                const uint32_t b = id[u];
+                const uint32_t b = MSD ? msd_bucket<DT>(raw[u], shift, f)
+                                       : model_bucket<DT>(M, raw[u], scale, offset, f, flags);
                 if (!(L.cur[b] & kSkipBit)) {
                     bk[u] = b;
                     rk[u] = atomicAdd(&L.tcnt[b], 1u);
@@ -894,9 +893,9 @@ __device__ __forceinline__ void scatter_body(const Task& T, gptr<const uint64_t>
 
 template <uint32_t KPT>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, uint32_t ntasks, uint64_t chunk,
-                                                             const uint16_t* ids, const uint64_t* pos,
+                                                             const double* models, const uint64_t* pos,
                                                              const uint8_t* skip, const uint32_t* task_flags,
-                                                             const LiveCounts* live)
+                                                             uint32_t flags, const LiveCounts* live)
 {
     if (live) {
         if (blockIdx.x >= live->chunks)
@@ -923,38 +922,48 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, 
         L.cur[b] = skip[(uint64_t)T.bucket_off + b] ? (c | kSkipBit) : c;
         L.tcnt[b] = 0;
     }
+    SModel M{};
+    const bool msd = T.kind == kMsd;
+    if (!msd)
+        load_model(M, models, T.model, T.leaves, L.model);
     __syncthreads();
     const uint64_t lo = (uint64_t)lc * chunk;
     const uint32_t n = (uint32_t)(min(T.n, lo + chunk) - lo);
     const gptr<const uint64_t> src = as_global<const uint64_t>((T.src ? T.scratch : T.keys) + T.start + lo);
     const gptr<uint64_t> dst = as_global((T.src ? T.keys : T.scratch) + T.start);
-    scatter_body<KPT>(T, src, ids + T.cnt_base + lo, dst, n, L, wsum);
+    if (T.dtype == kF64) {
+        if (msd) scatter_body<KPT, kF64, true>(T, M, src, dst, n, L, wsum, flags);
+        else scatter_body<KPT, kF64, false>(T, M, src, dst, n, L, wsum, flags);
+    } else {
+        if (msd) scatter_body<KPT, kU64, true>(T, M, src, dst, n, L, wsum, flags);
+        else scatter_body<KPT, kU64, false>(T, M, src, dst, n, L, wsum, flags);
+    }
 }
 
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
-                          const uint16_t* d_ids, const uint64_t* d_pos, const uint8_t* d_skip,
-                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, const LiveCounts* live,
-                          hipStream_t st)
+                          const double* d_models, const uint64_t* d_pos, const uint8_t* d_skip,
+                          const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, uint32_t max_leaves,
+                          uint32_t flags, const LiveCounts* live, hipStream_t st)
 {
     if (!total_chunks)
         return hipSuccess;
-    const size_t smem = scatter_lds_bytes(tile, max_fanout);
+    const size_t smem = scatter_lds_bytes(tile, max_fanout) + model_lds_bytes(max_leaves);
     switch (tile) {
     case 1024:
-        k_scatter<1><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
-                                                                  d_task_flags, live);
+        k_scatter<1><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,
+                                                                  d_task_flags, flags, live);
         break;
     case 2048:
-        k_scatter<2><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
-                                                                  d_task_flags, live);
+        k_scatter<2><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,
+                                                                  d_task_flags, flags, live);
         break;
     case 4096:
-        k_scatter<4><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
-                                                                  d_task_flags, live);
+        k_scatter<4><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,
+                                                                  d_task_flags, flags, live);
         break;
     case 8192:
-        k_scatter<8><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_ids, d_pos, d_skip,
-                                                                  d_task_flags, live);
+        k_scatter<8><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,
+                                                                  d_task_flags, flags, live);
         break;
     default:
         return hipErrorInvalidValue;

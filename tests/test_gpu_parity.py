@@ -143,7 +143,7 @@ def test_sort_matches_oracle(S, name, n):
 
 @pytest.mark.parametrize("kw", [dict(fanout=2), dict(fanout=16, leaves=8), dict(fanout=1000, leaves=1000),
                                 dict(fanout=4096, leaves=256, tile=4096), dict(tile=1024), dict(tile=8192),
-                                dict(tile=8192, fanout=2048), dict(tile=4096),
+                                dict(tile=8192, fanout=2048, leaves=256), dict(tile=4096),
                                 dict(base_threshold=2), dict(base_threshold=64, fanout=8),
                                 dict(base_threshold=4096, fanout=64), dict(sample_rate=0.5),
                                 dict(sample_cap=100), dict(leaves=1)])
@@ -158,12 +158,13 @@ def test_wide_tile_rounds_match_the_definition(S):
     # the automatic tile scatters rounds of at least 2^25 keys in 8192-key
     # tiles (the round-0 task here, and the over-full buckets after it);
     # a fixed 4096-key tile must give the same words
-    # fanout 2048 still leaves LDS room for the wide tile, fanout 4096 does
-    # not (those rounds keep 4096-key tiles)
+    # with the model (1024 leaves) in LDS beside it, fanout 1600 still leaves
+    # room for the wide tile (8192 * 10 + 1600 * 24 + 43080 bytes, the most a
+    # wide tile may take), fanouts 2048 and 4096 do not (those rounds keep
+    # smaller tiles)
     a = W.zipf_lognormal((1 << 25) + 12_345, seed=14, distinct=400_000)
     want = expected_sorted(a)
-    # (fanout 3072 takes the most LDS a wide tile may: 8192 * 10 + 3072 * 24 bytes)
-    for kw in (dict(), dict(tile=4096), dict(fanout=2048), dict(fanout=3072), dict(fanout=4096, leaves=512)):
+    for kw in (dict(), dict(tile=4096), dict(fanout=1600), dict(fanout=2048), dict(fanout=4096, leaves=512)):
         print("wide tile n=%d params=%s" % (a.size, kw), flush=True)
         got = gpu_sort(S, a, ls.params(**kw))
         assert np.array_equal(got, want)
