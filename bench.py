@@ -351,6 +351,70 @@ def bench_served(args, torch, ls):
     S.close()
 
 
+# The paper's synthetic workloads (Sec. 6.1 list; Sec. 6.4 scalability on Std
+# Normal and TwoDups from 1M to 1B doubles; Fig. 6 Zipf skew 0.50 - 0.99).
+SWEEP_POINTS = ([("normal", n) for n in (10 ** 6, 10 ** 7, 10 ** 8, 10 ** 9)] +
+                [("two_dups", n) for n in (10 ** 6, 10 ** 7, 10 ** 8, 10 ** 9)] +
+                [("zipf%.2f" % s, 10 ** 8) for s in (0.5, 0.6, 0.7, 0.8, 0.9, 0.99)] +
+                [(f, 10 ** 8) for f in ("root_dups", "mix_gauss", "chi_square", "exponential", "lognormal",
+                                        "uniform")])
+
+
+def library_sorted_words(t, torch):
+    """The definition of the result, computed independently of the library:
+    torch.sort (a radix sort) of the order words, turned back into the raw
+    words of the keys.  t: int64 view of the f64 keys."""
+    sign = torch.tensor(-(1 << 63), dtype=torch.int64, device=t.device)
+    neg = t < 0
+    ordw = torch.where(neg, ~t, t | sign)          # totalOrder word (unsigned order)
+    srt, _ = torch.sort(ordw ^ sign)               # signed order of (word ^ sign) = unsigned order of word
+    srt = srt ^ sign
+    return torch.where(srt < 0, srt & ~sign, ~srt)
+
+
+def bench_sweep(args, torch, ls):
+    """One JSON row per point of SWEEP_POINTS: keys/s of whole sorts (inputs
+    resident in HBM, a fresh copy per timed sort, copies outside the events)
+    and an exact check of the output against a library sort of the same keys
+    on the device."""
+    import workloads as W
+    S = ls.Sorter(0)
+    stream = torch.cuda.current_stream()
+    points = SWEEP_POINTS
+    if args.sweep_max_n:
+        points = [(f, n) for f, n in points if n <= args.sweep_max_n]
+    for fam, n in points:
+        t0 = time.perf_counter()
+        keys = W.paper_family_large(fam, n, seed=7)
+        gen_s = time.perf_counter() - t0
+        pristine = to_device(keys, torch)
+        del keys
+        work = torch.empty_like(pristine)
+        want = library_sorted_words(pristine.view(torch.int64), torch)
+        ms = []
+        for step in range(args.warmup + args.steps):
+            work.copy_(pristine)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            S.sort_(work)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if step >= args.warmup:
+                ms.append(e0.elapsed_time(e1))
+        exact = bool(torch.equal(work.view(torch.int64), want))
+        dups = int((want[1:] == want[:-1]).sum()) / n
+        m = sum(ms) / len(ms)
+        print(json.dumps({"metric": METRIC, "workload": "sweep", "family": fam, "n": n, "value": n / (m / 1e3),
+                          "unit": "keys/s", "ms_per_sort": m, "steps": args.steps, "dtype": "f64",
+                          "duplicate_ratio": dups, "exact_vs_library_sort": exact, "pipeline": S.last_stats(),
+                          "generated_s": gen_s}), flush=True)
+        del pristine, work, want
+        torch.cuda.empty_cache()
+        if not exact:
+            raise SystemExit("sweep point %s n=%d differs from the library sort" % (fam, n))
+    S.close()
+
+
 KERNEL_CLASS_OF = (("k_upload", "upload"), ("k_train", "train"), ("k_hist", "hist"), ("k_scan", "scan"),
                    ("k_classify", "classify"),
                    ("k_layout", "classify"), ("k_round_init", "classify"), ("k_scatter", "scatter"),
@@ -467,6 +531,7 @@ def main():
     ap.add_argument("--verify", action="store_true", help="check the sorted output against numpy")
     ap.add_argument("--segments", type=int, default=10_000, help="arrays of the segments workload")
     ap.add_argument("--requests", type=int, default=400, help="requests of the served workload")
+    ap.add_argument("--sweep-max-n", type=int, default=0, help="sweep workload: skip points above this size")
     ap.add_argument("--budget-gb", type=int, default=200)
     ap.add_argument("--inflight", type=int, default=1, help="served workload: batches in flight at once")
     ap.add_argument("--graph", choices=("on", "off"), default="off",
@@ -490,6 +555,8 @@ def main():
         return bench_segments(args, torch, ls)
     if args.workload == "served":
         return bench_served(args, torch, ls)
+    if args.workload == "sweep":
+        return bench_sweep(args, torch, ls)
 
     t_gen = time.perf_counter()
     keys, wname, n = make_workload(args.workload, args.n)

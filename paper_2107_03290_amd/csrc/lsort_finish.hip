@@ -23,12 +23,12 @@ namespace lsort {
 //     placed before it;
 //   * write the group out through LDS in order.
 // A group whose range is one value is copied.  A group with a mixed slot of
-// more than kBaseSlotMax keys (a fix-up of quadratic cost) is sorted by the
-// bitonic network of lds_bitonic instead.
+// more than kBaseSlotMax keys (a fix-up of quadratic cost) is marked and
+// sorted afterwards by k_base_slow with the bitonic network of lds_bitonic.
 //
 // Size classes: up to 1024 keys on 256 lanes, 4096 on 512, 8192 on 1024.
 // The grid is a few workgroups per CU; each workgroup strides over the list.
-constexpr uint32_t kBaseSlotMax = 48;
+constexpr uint32_t kBaseSlotMax = 64;
 
 // LDS: the group's order words, then per slot (at most CAP / 2 slots) the
 // count / start and the mixed flag.
@@ -94,9 +94,11 @@ __device__ __forceinline__ void mark_slow(const Group* groups, uint32_t g)
     *as_global(w) = *as_global(w) | kSlowMark;
 }
 
-// The groups of one size class that k_base marked: each workgroup scans a
-// stretch of the list, one descriptor per lane, and sorts the marked ones
-// with the bitonic network of lds_bitonic (groups of at most 16 NT keys).
+// The groups of one size class that k_base marked: workgroup b looks at
+// groups b, b + grid, b + 2 grid, ... (NT descriptors at a time, one per
+// lane), so marked groups are spread over the grid, and sorts the marked
+// ones with the bitonic network of lds_bitonic (groups of at most 16 NT
+// keys).
 template <uint32_t NT>
 __global__ __launch_bounds__(NT) void k_base_slow(Group* groups, uint32_t ngroups, const RoundCtl* gctl,
                                                   uint32_t cls)
@@ -110,13 +112,13 @@ __global__ __launch_bounds__(NT) void k_base_slow(Group* groups, uint32_t ngroup
     uint64_t* s = reinterpret_cast<uint64_t*>(smem);
     __shared__ uint32_t s_list[NT];
     __shared__ uint32_t s_cnt;
-    for (uint32_t base = blockIdx.x * NT; base < ngroups; base += gridDim.x * NT) {
+    for (uint64_t j0 = 0; blockIdx.x + j0 * gridDim.x < ngroups; j0 += NT) {
         if (threadIdx.x == 0)
             s_cnt = 0;
         __syncthreads();
-        const uint32_t g = base + threadIdx.x;
+        const uint64_t g = blockIdx.x + (j0 + threadIdx.x) * gridDim.x;
         if (g < ngroups && (as_global(&groups[g].dtype)[0] & kSlowMark))
-            s_list[atomicAdd(&s_cnt, 1u)] = g;
+            s_list[atomicAdd(&s_cnt, 1u)] = (uint32_t)g;
         __syncthreads();
         const uint32_t cnt = s_cnt;
         for (uint32_t j = 0; j < cnt; ++j) {
@@ -330,9 +332,9 @@ hipError_t launch_base(const Group* groups, uint32_t ngroups, uint32_t cls, cons
     Group* gm = const_cast<Group*>(groups);
     const size_t lds = (size_t)base_pad(kGroupClassCap[cls]) * 8;
     switch (cls) {
-    case 0: k_base_slow<64><<<std::min(grid, (ngroups + 63) / 64), 64, lds, st>>>(gm, ngroups, gctl, 0); break;
-    case 1: k_base_slow<256><<<std::min(grid, (ngroups + 255) / 256), 256, lds, st>>>(gm, ngroups, gctl, 1); break;
-    case 2: k_base_slow<512><<<std::min(grid, (ngroups + 511) / 512), 512, lds, st>>>(gm, ngroups, gctl, 2); break;
+    case 0: k_base_slow<64><<<grid, 64, lds, st>>>(gm, ngroups, gctl, 0); break;
+    case 1: k_base_slow<256><<<grid, 256, lds, st>>>(gm, ngroups, gctl, 1); break;
+    case 2: k_base_slow<512><<<grid, 512, lds, st>>>(gm, ngroups, gctl, 2); break;
     }
     return hipGetLastError();
 }

@@ -537,6 +537,14 @@ def test_twodups_duplicate_ratio_near_paper():
     assert 0.80 <= d <= 0.96
 
 
+def test_zipf_duplicate_ratio_near_paper():
+    # Sec. 3: a Zipfian input of skew 0.9 holds 72% duplicates (universe
+    # unstated; the generator draws ranks 1..n).
+    d = W.duplicate_ratio(W.paper_family("zipf0.9", 1_000_000, seed=3))
+    assert 0.62 <= d <= 0.80
+    assert W.duplicate_ratio(W.paper_family("zipf0.5", 1_000_000, seed=3)) < d
+
+
 def test_rootdups_duplicate_ratio_closed_form():
     n = 1_000_000
     assert W.duplicate_ratio(W.root_dups(n)) == 1.0 - math.isqrt(n) / n

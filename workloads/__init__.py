@@ -277,10 +277,70 @@ def paper_family(name: str, n: int, seed: int = 7) -> np.ndarray:
     if name == "mix_gauss":
         return mix_gauss(n, seed)
     if name.startswith("zipf"):
+        # ranks 1..n: the universe is unstated; n ranks gives skew 0.9 the
+        # paper's 72% duplicates (Sec. 3)
         skew = float(name[4:] or 0.9)
-        ranks = np.searchsorted(zipf_table(max(1, n // 10), skew), r.random(n), side="right")
+        ranks = np.searchsorted(zipf_table(n, skew), r.random(n), side="right")
         return ranks.astype(np.float64)
     raise KeyError(name)
+
+
+def paper_family_large(name: str, n: int, seed: int = 7) -> np.ndarray:
+    """paper_family for sizes up to 10^9, drawn CHUNK keys at a time in
+    threads (each piece from its own stream, so the values do not depend on
+    the thread count; they differ from paper_family's single stream)."""
+    if n <= CHUNK:
+        return paper_family(name, n, seed)
+    out = np.empty(n, dtype=np.float64)
+    if name in ("root_dups", "two_dups"):
+        nn = np.uint64(n)
+        root = np.uint64(max(1, math.isqrt(n)))
+
+        def fill(c, lo, hi):
+            i = np.arange(lo, hi, dtype=np.uint64)
+            if name == "root_dups":
+                out[lo:hi] = (i % root).astype(np.float64)
+            else:       # n < 2^32 keeps i * i inside 64 bits
+                out[lo:hi] = (((i * i) % nn + np.uint64(n // 2)) % nn).astype(np.float64)
+
+        if name == "two_dups" and n >= (1 << 32):
+            raise ValueError("two_dups needs n < 2^32")
+        _chunked(n, fill)
+        return out
+    if name == "mix_gauss":
+        r = _rng(seed)
+        k = 5
+        means = r.uniform(-100.0, 100.0, size=k)
+        sds = r.uniform(0.5, 20.0, size=k)
+        w = r.random(k)
+        w /= w.sum()
+    if name.startswith("zipf"):
+        skew = float(name[4:] or 0.9)
+        cdf = zipf_table(n, skew)
+
+    def fill(c, lo, hi):
+        g = _rng(seed, 1 + c)
+        m = hi - lo
+        if name == "uniform":
+            out[lo:hi] = g.uniform(0.0, float(n), size=m)
+        elif name == "normal":
+            out[lo:hi] = g.normal(0.0, 1.0, size=m)
+        elif name == "lognormal":
+            out[lo:hi] = g.lognormal(0.0, 0.5, size=m)
+        elif name == "chi_square":
+            out[lo:hi] = g.chisquare(4.0, size=m)
+        elif name == "exponential":
+            out[lo:hi] = g.exponential(1.0 / 2.0, size=m)
+        elif name == "mix_gauss":
+            comp = g.choice(k, size=m, p=w)
+            out[lo:hi] = g.normal(means[comp], sds[comp])
+        elif name.startswith("zipf"):
+            out[lo:hi] = np.searchsorted(cdf, g.random(m), side="right").astype(np.float64)
+        else:
+            raise KeyError(name)
+
+    _chunked(n, fill)
+    return out
 
 
 def duplicate_ratio(a: np.ndarray) -> float:
