@@ -255,10 +255,7 @@ def bench_served(args, torch, ls):
           file=sys.stderr, flush=True)
     # graph mode (LS_FLAG_GRAPH): requests and batches of up to 2^22 keys run
     # as replays of captured graphs, on the plain path and in the server
-    if args.graph == "on":
-        raise SystemExit("--graph on is not available for the served workload: the server runs host-driven "
-                         "batches (graph replays in the server are switched off)")
-    gp = ls.params()
+    gp = ls.params(flags=ls.FLAG_GRAPH if args.graph == "on" else 0)
     pristine = [to_device(a, torch) for a in reqs]
     work = [torch.empty_like(t) for t in pristine]
     ref = [torch.empty_like(t) for t in pristine]

@@ -235,8 +235,8 @@ typedef struct ls_server ls_server;
  * they need (keys already resident + the library's scratch) stays within
  * hbm_budget_bytes, batches the admitted ones into segmented sorts, and
  * keeps up to max_inflight batches in flight on separate streams.  p may be
- * NULL (the defaults).  p->flags with LS_FLAG_GRAPH is rejected with
- * LS_ERR_UNSUPPORTED: served batches run host-driven. */
+ * NULL (the defaults).  With LS_FLAG_GRAPH in p->flags, batches of at most
+ * 2^22 keys run as replays of graphs each worker captures per size class. */
 ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
                            uint32_t max_inflight, const ls_params* p);
 

@@ -188,10 +188,6 @@ ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
         return LS_ERR_INVALID;
     if (p && p->struct_size != sizeof(ls_params))
         return LS_ERR_INVALID;
-    // Batches as graph replays are switched off in the server: a served run
-    // with them ended in a host segmentation fault whose cause is not known.
-    if (p && (p->flags & LS_FLAG_GRAPH))
-        return LS_ERR_UNSUPPORTED;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
         return LS_ERR_INVALID;

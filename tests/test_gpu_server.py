@@ -1,6 +1,7 @@
 """The continuous-batching server: every request's result is the same alone
-and in the mix (bit-exact), admission respects the HBM budget, and requests
-that arrive while batches run are picked up."""
+and in the mix (bit-exact), admission respects the HBM budget, requests that
+arrive while batches run are picked up, and batches replayed from captured
+HIP graphs give the same bits."""
 import threading
 
 import numpy as np
@@ -108,6 +109,27 @@ def test_concurrent_submitters_while_batches_run():
             x.start()
         for x in th:
             x.join()
+        for tk in tickets:
+            srv.wait(tk)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["completed"] == len(ts)
+    for a, t in zip(reqs, ts):
+        assert np.array_equal(words(t), expected_sorted(a))
+
+
+def test_graph_batches_in_the_server(S):
+    spec = W.request_spec(count=40, seed=34, lo=1, hi=1 << 23)
+    # batches of up to 2^22 keys replay graphs captured by two workers at
+    # once; larger batches run host-driven in between on the same contexts
+    reqs = [W.request_keys(spec, i) for i in range(40)]
+    ts = [upload(a) for a in reqs]
+    torch.cuda.synchronize()
+    print("server+graph: %d requests, %d keys" % (len(reqs), sum(a.size for a in reqs)), flush=True)
+    srv = ls.Server(0, hbm_budget=4 << 30, max_inflight=2, p=ls.params(flags=ls.FLAG_GRAPH))
+    try:
+        tickets = [srv.submit(t) for t in ts]
         for tk in tickets:
             srv.wait(tk)
         st = srv.stats()
