@@ -66,15 +66,22 @@ typedef enum { LS_F64 = 1, LS_U64 = 2 } ls_dtype;
                                          as without the flag.  Ignored with LS_FLAG_PROFILE or
                                          LS_FLAG_DEBUG_TOUCHUP and for larger batches. */
 
+#define LS_FLAG_INPLACE        0x20u  /* partition in place (Alg. 1: fragments of 64 keys written back into the
+                                         input, then Defragment as a block permutation) instead of through a
+                                         scratch buffer of n keys: extra device memory per round is about 3% of
+                                         the keys' bytes.  Fanout is capped at 128.  Same results; slower. */
+
 /* Tuning parameters (Sec. 6.1 gives f = 1000, c = 100, L = 1000, 1% sample).
  * Zero fields take the library defaults.  None of them changes the result. */
 typedef struct {
     uint32_t struct_size;      /* sizeof(ls_params) */
     uint32_t fanout;           /* f: buckets per partition, 2..4096 (default 1024) */
     uint32_t leaves;           /* L: leaf models of the two-layer model, 1..1024 (default 1024) */
-    uint32_t tile;             /* keys staged per scatter tile in LDS: 1024, 2048, 4096 or 8192, or 0
-                                  (ls_default_params) for automatic: 4096, and 8192 in host-driven rounds
-                                  of at least 2^25 keys whose fanouts leave room for it in LDS */
+    uint32_t tile;             /* keys staged per scatter tile in LDS: at most 1024, 2048, 4096 or 8192
+                                  (halved down to 1024 while the tile, the fanout's tables and the model
+                                  exceed a workgroup's LDS), or 0 (ls_default_params) for automatic: 4096,
+                                  and 8192 in host-driven rounds of at least 2^25 keys whose fanouts leave
+                                  room for it in LDS */
     uint32_t base_threshold;   /* buckets of at most this many keys are sorted in LDS, in groups of < 2x (default 4096, max 4096) */
     uint32_t flags;            /* LS_FLAG_* */
     double   sample_rate;      /* model training sample (default 0.01) */
@@ -103,6 +110,17 @@ ls_status ls_workspace_size(ls_ctx* ctx, ls_dtype dtype, size_t n, const ls_para
 
 /* Allocate scratch for sorts of up to n keys ahead of time. */
 ls_status ls_reserve(ls_ctx* ctx, size_t n, const ls_params* p);
+
+/* Device memory the context holds now, in bytes: the sum of its work buffers
+ * (scratch keys, round tables, output lists, training samples), which it
+ * keeps between sorts and grows on demand.  Not counted: the library's code
+ * and static data, and what the HIP runtime allocates for itself.  Waits for
+ * nothing; call it when no sort of this context is being issued. */
+ls_status ls_device_bytes(ls_ctx* ctx, size_t* bytes);
+
+/* Wait for the context's queued work, then free all its work buffers (the
+ * next sort allocates them again).  Graphs recorded on them are dropped. */
+ls_status ls_trim(ls_ctx* ctx);
 
 /* Sort n keys of d_keys in place (Alg. 2).  d_keys: device pointer to n
  * contiguous 8-byte keys, 8-byte aligned.  p may be NULL (defaults). */

@@ -26,6 +26,7 @@ FLAG_SYNC = 0x2
 FLAG_NONMONOTONE = 0x4
 FLAG_PROFILE = 0x8
 FLAG_GRAPH = 0x10
+FLAG_INPLACE = 0x20
 
 
 def FLAG_PROFILE_ONLY(k: int) -> int:
@@ -46,7 +47,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime er
 
 # C-ABI entry points declared in include/lsort.h
 EXPORTS = (
-    "ls_create", "ls_destroy", "ls_default_params", "ls_workspace_size", "ls_reserve",
+    "ls_create", "ls_destroy", "ls_default_params", "ls_workspace_size", "ls_reserve", "ls_device_bytes", "ls_trim",
     "ls_sort_f64", "ls_sort_u64", "ls_sort_noalloc", "ls_sort_segments", "ls_sort_arrays", "ls_autotune", "ls_sync",
     "ls_last_stats", "ls_last_profile", "ls_profile_reset", "ls_status_string", "ls_last_error",
     "ls_model_train", "ls_stage_hist",
@@ -106,6 +107,8 @@ def lib() -> ctypes.CDLL:
             L.ls_default_params.restype = None
             L.ls_workspace_size.argtypes = [vp, ctypes.c_int, sz, P(Params), P(sz)]
             L.ls_reserve.argtypes = [vp, sz, P(Params)]
+            L.ls_device_bytes.argtypes = [vp, P(sz)]
+            L.ls_trim.argtypes = [vp]
             L.ls_sort_f64.argtypes = [vp, vp, sz, vp, P(Params)]
             L.ls_sort_u64.argtypes = [vp, vp, sz, vp, P(Params)]
             L.ls_sort_noalloc.argtypes = [vp, ctypes.c_int, vp, sz, vp, P(Params)]
@@ -281,6 +284,16 @@ class Sorter:
 
     def profile_reset(self):
         self._check(lib().ls_profile_reset(self._ctx))
+
+    def device_bytes(self) -> int:
+        """Device memory the context's work buffers hold now."""
+        b = ctypes.c_size_t()
+        self._check(lib().ls_device_bytes(self._ctx, ctypes.byref(b)))
+        return b.value
+
+    def trim(self):
+        """Free the context's work buffers (after its queued work ends)."""
+        self._check(lib().ls_trim(self._ctx))
 
     def workspace_size(self, n: int, dtype: int = F64, p: Params | None = None) -> int:
         b = ctypes.c_size_t()

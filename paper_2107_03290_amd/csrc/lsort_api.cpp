@@ -99,6 +99,11 @@ struct ls_ctx {
     DevBuf scratch, tune, models, sample, sample2, tbest, tfirst, tnf, gjobs, ljobs, tasks, next, cnt, pos, scantmp,
         bstat,
         skip, tflags, fills, ctl;
+    // in-place rounds (LS_FLAG_INPLACE): partial counts and their scan, the
+    // bucket plans, full blocks per bucket, overflow blocks, block tags and
+    // read flags, the side buffer of open fragments
+    DevBuf pcnt, ppos, ipb, fullb, ovf, tags, done, sidebuf;
+    uint32_t ip_epoch = 0;
     DevBuf groups[kGroupClasses];
     PinBuf pin_jobs;
     PinBuf estage;                   // round-0 lists of a host-driven sort (read by the upload kernel)
@@ -375,6 +380,8 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
     }
     if (P.fanout < 2 || P.fanout > kMaxFanout)
         return fail(C, LS_ERR_INVALID, "fanout must be in [2, 4096]");
+    if (P.flags & LS_FLAG_INPLACE)   // one open fragment per bucket in LDS
+        P.fanout = std::min(P.fanout, kIpFanout);
     if (P.leaves < 1 || P.leaves > kMaxLeaves)
         return fail(C, LS_ERR_INVALID, "leaves must be in [1, 1024]");
     if (P.tile != 1024 && P.tile != 2048 && P.tile != 4096 && P.tile != 8192)
@@ -386,11 +393,12 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
     // the scatter holds the staged tile, per-bucket tables and the model
     const size_t model_lds = model_lds_bytes(P.leaves);
     auto scatter_lds = [&](uint32_t tile) { return scatter_lds_bytes(tile, P.fanout) + model_lds + 128; };
-    if (P.tile_wide)   // automatic tile: the largest of 4096, 2048, 1024 that fits
-        while (P.tile > 1024 && scatter_lds(P.tile) > C->lds_limit)
-            P.tile /= 2;
+    // the largest tile up to the given (or automatic) one that fits
+    while (P.tile > 1024 && scatter_lds(P.tile) > C->lds_limit)
+        P.tile /= 2;
     size_t hist_lds = (((size_t)P.fanout * 20 + 15) & ~(size_t)15) + model_lds + 64;
-    if (scatter_lds(P.tile) > C->lds_limit || hist_lds > C->lds_limit)
+    if (scatter_lds(P.tile) > C->lds_limit || hist_lds > C->lds_limit ||
+        ((P.flags & LS_FLAG_INPLACE) && ip_frag_lds_bytes(P.fanout, P.leaves) + 128 > C->lds_limit))
         return fail(C, LS_ERR_UNSUPPORTED, "tile/fanout/leaves exceed the LDS of one workgroup");
     // automatic tile: the wide tile is taken only by rounds whose fanouts fit
     P.wide_max_fanout = 0;
@@ -423,10 +431,13 @@ struct Trainer {
         J.leaves = L;
         J.dtype = dtype;
         J.block0 = blocks;
-        J.nblocks = (uint32_t)((m + kSampleBlock - 1) / kSampleBlock);
+        // (a job whose sample fits one LDS run takes no room in the sample
+        // buffers and leaf tables: it trains in one workgroup)
+        const bool sampled = m > kSampleBlock;
+        J.nblocks = sampled ? (uint32_t)((m + kSampleBlock - 1) / kSampleBlock) : 0u;
         max_sample = std::max(max_sample, m);
-        samples += m;
-        leaves += L;
+        samples += sampled ? m : 0;
+        leaves += sampled ? L : 0;
         models += model_doubles(L);
         blocks += J.nblocks;
         jobs.push_back(J);
@@ -441,17 +452,20 @@ ls_status train(ls_ctx* C, const DevBuf& jobs, uint32_t njobs, uint32_t blocks, 
     if (!njobs)
         return LS_OK;
     TRY(ensure(C, C->models, (model_base + models) * sizeof(double), st, model_base * sizeof(double)));
-    TRY(ensure(C, C->sample, samples * 8, st));
-    TRY(ensure(C, C->sample2, samples * 8, st));
-    // the per-leaf and per-job tables start at zero and the fit kernel
-    // leaves them at zero; only freshly allocated memory needs clearing
-    DevBuf* tabs[3] = {&C->tbest, &C->tfirst, &C->tnf};
-    const size_t need[3] = {leafs * 8, leafs * 8, (size_t)njobs * 16};
-    for (int i = 0; i < 3; ++i) {
-        const void* before = tabs[i]->p;
-        TRY(ensure(C, *tabs[i], need[i], st));
-        if (tabs[i]->p != before)
-            HIPCHECK(C, hipMemsetAsync(tabs[i]->p, 0, tabs[i]->cap, st));
+    // jobs whose sample fits one LDS run need no global buffers
+    if (max_sample > kSampleBlock) {
+        TRY(ensure(C, C->sample, samples * 8, st));
+        TRY(ensure(C, C->sample2, samples * 8, st));
+        // the per-leaf and per-job tables start at zero and the fit kernel
+        // leaves them at zero; only freshly allocated memory needs clearing
+        DevBuf* tabs[3] = {&C->tbest, &C->tfirst, &C->tnf};
+        const size_t need[3] = {leafs * 8, leafs * 8, (size_t)njobs * 16};
+        for (int i = 0; i < 3; ++i) {
+            const void* before = tabs[i]->p;
+            TRY(ensure(C, *tabs[i], need[i], st));
+            if (tabs[i]->p != before)
+                HIPCHECK(C, hipMemsetAsync(tabs[i]->p, 0, tabs[i]->cap, st));
+        }
     }
     if (prof)
         prof->begin(0);
@@ -517,10 +531,12 @@ struct Batch {
 void prepare(std::vector<Array>& arrays, void* scratch, const Params& P, bool msd_only, Batch& B)
 {
     const uint32_t lf = 31u - (uint32_t)__builtin_clz(P.fanout);
+    // in-place rounds keep every key in the caller's buffer
+    const bool inplace = (P.flags & LS_FLAG_INPLACE) != 0;
     uint64_t off = 0;
     for (uint32_t i = 0; i < arrays.size(); ++i) {
         Array& a = arrays[i];
-        a.scratch = (uint64_t*)scratch + off;
+        a.scratch = inplace ? a.keys : (uint64_t*)scratch + off;
         off += a.n;
         if (a.n <= 1)
             continue;
@@ -537,11 +553,13 @@ void prepare(std::vector<Array>& arrays, void* scratch, const Params& P, bool ms
         t.seg = i;
         if (msd_only) {
             t.kind = kMsd;
-            t.fanout = 1u << lf;
+            t.fanout = inplace ? ip_fanout(a.n, 1u << lf) : 1u << lf;
             t.shift = 64 - lf;
         } else {
             t.kind = kGlobal;
             t.fanout = child_fanout(a.n, P.base, P.fanout);
+            if (inplace)
+                t.fanout = ip_fanout(a.n, t.fanout);
             t.scale = (double)t.fanout;
             t.leaves = P.leaves;
             t.model = B.tr.add(a.keys, a.n, sample_size(a.n, P.rate, P.cap), P.seed, P.leaves, a.dtype);
@@ -624,6 +642,10 @@ LayoutParams layout_params(const Params& P, uint64_t model_base)
     lp.tile_wide = P.tile_wide;
     lp.wide_keys = kWideTileKeys;
     lp.wide_max_fanout = P.wide_max_fanout;
+    // in-place rounds: one chunk per CU, so that the open fragments left at
+    // the chunks' ends (side buffer) stay a small fraction of the keys
+    lp.target_chunks = (P.flags & LS_FLAG_INPLACE) ? kSmallRoundChunks : kTargetChunks;
+    lp.inplace = (P.flags & LS_FLAG_INPLACE) ? 1u : 0u;
     lp.rate = P.rate;
     lp.cap = P.cap;
     lp.seed = P.seed;
@@ -638,6 +660,8 @@ LayoutParams layout_params(const Params& P, uint64_t model_base)
 
 ls_status check_overflow(ls_ctx* C)
 {
+    if (C->h_ctl->overflow & 2u)
+        return fail(C, LS_ERR_HIP, "in-place block permutation: a block slot was not released in time");
     if (C->h_ctl->overflow)
         return fail(C, LS_ERR_HIP, "a partition round exceeded its buffers (internal size bound)");
     return LS_OK;
@@ -660,6 +684,23 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         TRY(ensure(C, C->bstat, (uint64_t)R.buckets * 16, st));
         TRY(ensure(C, C->skip, R.buckets, st));
         TRY(ensure(C, C->tflags, (size_t)nt * 4, st));
+        const bool inplace = (P.flags & LS_FLAG_INPLACE) != 0;
+        const uint64_t gslots = R.nkeys / kIpBlock + nt + 1;   // block slots of the round's tasks
+        if (inplace) {
+            TRY(ensure(C, C->pcnt, R.entries * 4, st));
+            TRY(ensure(C, C->ppos, R.entries * 8, st));
+            TRY(ensure(C, C->ipb, R.buckets * sizeof(IpBucket), st));
+            TRY(ensure(C, C->fullb, (R.buckets + 1) / 2 * 8, st));
+            TRY(ensure(C, C->ovf, R.buckets * kIpBlock * 8, st));
+            TRY(ensure(C, C->tags, gslots * 2, st));
+            TRY(ensure(C, C->sidebuf, std::max<size_t>(R.side_keys, 1) * 8, st));
+            // read flags hold the epoch of the round that released the slot
+            // (never 0, the value of a cleared flag)
+            const void* before = C->done.p;
+            TRY(ensure(C, C->done, (gslots + 1) / 2 * 8, st));
+            if (C->done.p != before)
+                HIPCHECK(C, launch_zero(C->done.p, C->done.cap / 8 * 8, st));
+        }
         // Output lists, sized by what classify can emit: a next-round task
         // is a bucket of at least 2T keys; a fill bucket holds at least
         // max(T/8, 2) keys (plus one piece per kFillPiece keys); a group of
@@ -697,15 +738,29 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         lp.cap_tasks = std::min(C->next.cap / sizeof(Task), C->ljobs.cap / sizeof(ModelJob));
         HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, R.buckets, (RoundCtl*)C->ctl.p, false, st));
         prof.begin(1);
-        HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
-                                (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, R.max_fanout, R.max_leaves, flags,
-                                nullptr, st));
-        // the method reads each key once
-        prof.end((double)R.nkeys * 8.0);
+        if (inplace) {
+            // fragments written back into each chunk (Alg. 1): every key read
+            // and written once
+            HIPCHECK(C, launch_zero(C->fullb.p, (R.buckets + 1) / 2 * 8, st));
+            HIPCHECK(C, launch_ip_frag((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
+                                       (uint32_t*)C->cnt.p, (uint32_t*)C->pcnt.p, (uint32_t*)C->fullb.p,
+                                       (uint64_t*)C->bstat.p, (uint16_t*)C->tags.p, (uint64_t*)C->sidebuf.p,
+                                       R.max_fanout, R.max_leaves, flags, st));
+            prof.end((double)R.nkeys * 16.0);
+        } else {
+            HIPCHECK(C, launch_hist((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
+                                    (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, R.max_fanout, R.max_leaves, flags,
+                                    nullptr, st));
+            // the method reads each key once
+            prof.end((double)R.nkeys * 8.0);
+        }
         prof.begin(2);
         HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, R.entries, (uint64_t*)C->scantmp.p,
                                 nullptr, st));
-        prof.end((double)R.entries * 16.0);
+        if (inplace)
+            HIPCHECK(C, launch_scan((const uint32_t*)C->pcnt.p, (uint64_t*)C->ppos.p, R.entries,
+                                    (uint64_t*)C->scantmp.p, nullptr, st));
+        prof.end((double)R.entries * (inplace ? 32.0 : 16.0));
         prof.begin(3);
         arm_publish(C);
         HIPCHECK(C, launch_classify((const Task*)C->tasks.p, nt, (const uint64_t*)C->pos.p,
@@ -716,13 +771,30 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
         prof.end((double)R.buckets * 32.0);
         const size_t scatter_rec = prof.recs.size();
         prof.begin(4);
-        HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
-                                   (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
-                                   (const uint32_t*)C->tflags.p, R.tile, R.max_fanout, R.max_leaves, flags, nullptr,
-                                   st));
-        prof.end(0.0);
+        if (inplace) {
+            // Defragment: blocks to their buckets' slots, then the open
+            // fragments and overflow blocks to the rest of each bucket
+            HIPCHECK(C, launch_ip_plan((const Task*)C->tasks.p, nt, R.buckets, (const uint64_t*)C->pos.p,
+                                       (const uint32_t*)C->fullb.p, (IpBucket*)C->ipb.p, st));
+            HIPCHECK(C, launch_ip_permute((const Task*)C->tasks.p, nt, R.buckets, gslots, (IpBucket*)C->ipb.p,
+                                          (const uint16_t*)C->tags.p, (uint32_t*)C->done.p, (uint64_t*)C->ovf.p,
+                                          C->ip_epoch = C->ip_epoch + 1 ? C->ip_epoch + 1 : 1u, (RoundCtl*)C->ctl.p,
+                                          st));
+            HIPCHECK(C, launch_ip_gather((const Task*)C->tasks.p, nt, R.chunks, R.chunk, R.buckets,
+                                         (const uint32_t*)C->pcnt.p,
+                                         (const uint64_t*)C->ppos.p, (const IpBucket*)C->ipb.p,
+                                         (const uint64_t*)C->sidebuf.p, (const uint64_t*)C->ovf.p, st));
+            // every key read and written once more (blocks and the rest)
+            prof.end((double)R.nkeys * 16.0);
+        } else {
+            HIPCHECK(C, launch_scatter((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
+                                       (const uint64_t*)C->pos.p, (const uint8_t*)C->skip.p,
+                                       (const uint32_t*)C->tflags.p, R.tile, R.max_fanout, R.max_leaves, flags,
+                                       nullptr, st));
+            prof.end(0.0);
+        }
         TRY(wait_published(C, st));
-        if (prof.recs.size() > scatter_rec) {
+        if (!inplace && prof.recs.size() > scatter_rec) {
             // scatter: reads every key of a task that progressed and writes
             // those not in all-equal buckets
             const double moved = (double)(R.nkeys - (C->h_ctl->stall_keys - R.stall_keys));
@@ -1067,7 +1139,8 @@ void drop_graphs(ls_ctx* C, bool all)
 
 bool graph_eligible(uint64_t total, size_t narrays, const Params& P)
 {
-    return (P.flags & LS_FLAG_GRAPH) && !(P.flags & (LS_FLAG_PROFILE | LS_FLAG_DEBUG_TOUCHUP)) && total > 0 &&
+    return (P.flags & LS_FLAG_GRAPH) && !(P.flags & (LS_FLAG_PROFILE | LS_FLAG_DEBUG_TOUCHUP | LS_FLAG_INPLACE)) &&
+           total > 0 &&
            total <= kGraphMaxKeys && narrays <= kGraphMaxArrays;
 }
 
@@ -1144,12 +1217,13 @@ ls_status run_graph(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const
 // not hold would end the sort with an error, never write past a buffer.
 
 // The context's device buffers, in one list (save, carve, restore, free).
-constexpr size_t kCtxBufs = 23;
+constexpr size_t kCtxBufs = 31;
 std::array<DevBuf*, kCtxBufs> ctx_bufs(ls_ctx* C)
 {
     return {&C->scratch, &C->tune, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst,
             &C->tnf, &C->gjobs, &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
-            &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2]};
+            &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2],
+            &C->pcnt, &C->ppos, &C->ipb, &C->fullb, &C->ovf, &C->tags, &C->done, &C->sidebuf};
 }
 
 struct Carve {
@@ -1231,7 +1305,8 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
         TRY(run_graph(C, arrays, st, P, B));
         return conclude(C, arrays, st, P, msd_only);
     }
-    TRY(ensure(C, C->scratch, std::max<uint64_t>(total, 1) * 8, st));
+    if (!(P.flags & LS_FLAG_INPLACE))
+        TRY(ensure(C, C->scratch, std::max<uint64_t>(total, 1) * 8, st));
     TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
     prepare(arrays, C->scratch.p, P, msd_only, B);
     const uint64_t global_models = B.tr.models;
@@ -1415,6 +1490,36 @@ ls_status ls_reserve(ls_ctx* C, size_t n, const ls_params* p)
     return ensure(C, C->scratch, std::max<size_t>(n, 1) * 8, nullptr);
 }
 
+ls_status ls_device_bytes(ls_ctx* C, size_t* bytes)
+{
+    if (!C || !bytes)
+        return LS_ERR_INVALID;
+    size_t s = 0;
+    for (DevBuf* b : ctx_bufs(C))
+        if (b->p)
+            s += b->cap;
+    *bytes = s;
+    return LS_OK;
+}
+
+ls_status ls_trim(ls_ctx* C)
+{
+    GateUse gate;
+    if (!C)
+        return LS_ERR_INVALID;
+    HIPCHECK(C, hipSetDevice(C->device));
+    HIPCHECK(C, hipDeviceSynchronize());
+    drop_graphs(C, true);
+    for (DevBuf* b : ctx_bufs(C)) {
+        if (b->p)
+            HIPCHECK(C, hipFree(b->p));
+        b->p = nullptr;
+        b->cap = 0;
+    }
+    ++C->gen;
+    return LS_OK;
+}
+
 ls_status ls_sort_f64(ls_ctx* C, double* d_keys, size_t n, ls_stream_t stream, const ls_params* p)
 {
     if (!C)
@@ -1448,8 +1553,9 @@ ls_status ls_sort_noalloc(ls_ctx* C, ls_dtype dtype, void* d_keys, size_t n, ls_
                                                " keys; got " + std::to_string(n));
     Params P;
     TRY(resolve(C, p, P));
-    if (P.flags & (LS_FLAG_PROFILE | LS_FLAG_GRAPH))
-        return fail(C, LS_ERR_UNSUPPORTED, "ls_sort_noalloc takes neither LS_FLAG_PROFILE nor LS_FLAG_GRAPH");
+    if (P.flags & (LS_FLAG_PROFILE | LS_FLAG_GRAPH | LS_FLAG_INPLACE))
+        return fail(C, LS_ERR_UNSUPPORTED,
+                    "ls_sort_noalloc takes none of LS_FLAG_PROFILE, LS_FLAG_GRAPH, LS_FLAG_INPLACE");
     if (!C->na_base)
         return fail(C, LS_ERR_HIP, "the no-allocation array of this device was not found");
     size_t need = 0;

@@ -195,6 +195,20 @@ __device__ __forceinline__ uint32_t msd_bucket(uint64_t raw, uint32_t shift, uin
     return (uint32_t)((to_ord(raw, DT) >> shift) & (uint64_t)(fanout - 1u));
 }
 
+// ------------------------------------------------------------ task lists --
+
+// The task of a round that owns chunk `chunk` (tasks are laid out with
+// increasing chunk0).
+__device__ __forceinline__ uint32_t find_task(const Task* tasks, uint32_t ntasks, uint32_t chunk)
+{
+    uint32_t lo = 0, hi = ntasks;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (tasks[mid].chunk0 <= chunk) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------ workgroup order --
 
 // Workgroups of a launch are handed to the eight XCDs in turn (workgroup b

@@ -54,6 +54,7 @@ struct Task {
     uint64_t cnt_base;    // sum of the sizes of the round's earlier tasks
     uint32_t seg;
     uint32_t pad;
+    uint64_t side_off;    // in-place rounds: first key of this task's part of the side buffer
 };
 
 // A run of adjacent small buckets sorted by one workgroup in LDS.
@@ -102,6 +103,8 @@ struct LayoutParams {
     uint32_t tile_wide;   // tile of rounds of at least wide_keys keys (0: always `tile`)
     uint64_t wide_keys;
     uint32_t wide_max_fanout;   // largest task fanout whose wide-tile scatter fits in LDS
+    uint32_t target_chunks;     // chunks a large round is cut into (kTargetChunks; in-place rounds fewer)
+    uint32_t inplace;           // in-place rounds (LS_FLAG_INPLACE)
     uint32_t pad;
     double rate;
     uint64_t cap;
@@ -117,6 +120,51 @@ struct LayoutParams {
     // none).  The host then reads the next round's sizes and queues its
     // launches while the rest of the round (the scatter) still runs.
     uint64_t* host_flag;
+};
+
+// In-place partition (LS_FLAG_INPLACE): keys per block and the largest
+// fanout (the LDS holds one open fragment of a block per bucket).
+constexpr uint32_t kIpBlock = 64;
+constexpr uint32_t kIpFanout = 128;
+// Fewest leaves of a local model in an in-place round (which otherwise gets
+// 8 leaves per bucket).
+constexpr uint32_t kIpMinLeaves = 16;
+
+// Chunks of an in-place round hold at least kIpChunkBlocks x fanout blocks,
+// and a task of n keys has a fanout of at most n / (kIpChunkBlocks kIpBlock):
+// the open fragments a chunk leaves (fewer than fanout x kIpBlock keys) and
+// the overflow blocks (at most one per bucket) each stay under 1/64 of the
+// keys.
+constexpr uint64_t kIpChunkBlocks = 64;
+
+// Fanout of a task of n keys in an in-place round: at most the out-of-place
+// choice fc, and at most n / (kIpChunkBlocks kIpBlock) (at least 2).  A power
+// of two when fc is one.
+__host__ __device__ inline uint32_t ip_fanout(uint64_t n, uint32_t fc)
+{
+    const uint64_t lim = n / (kIpChunkBlocks * kIpBlock);
+    uint32_t f = 2;
+    while ((uint64_t)f * 2 <= lim && f * 2 <= fc)
+        f *= 2;
+    return f < fc ? f : fc;
+}
+
+// Keys of the side buffer one chunk of an in-place task may fill.
+__host__ __device__ inline uint64_t ip_side_keys(uint64_t chunk, uint32_t fanout)
+{
+    const uint64_t most = (uint64_t)fanout * (kIpBlock - 1);
+    return chunk < most ? chunk : most;
+}
+
+// A bucket of an in-place round: its range [start, end) in the task's final
+// layout; its full blocks go to the slots [a, dend) (one more that does not
+// fit goes to an overflow block); its area of slots to read out starts at
+// `area`; `ptr` holds the write pointer w (low 32 bits) and the read pointer
+// r (high 32 bits, signed) of the block permutation.
+struct IpBucket {
+    uint64_t ptr;
+    uint64_t start, end;
+    uint32_t a, area, dend, full, task, pad;
 };
 
 // Sizes of the running round, copied from the control block when the round
@@ -157,6 +205,7 @@ struct RoundCtl {
     uint32_t tile;                    // scatter tile of the next round (written by the layout)
     uint32_t pad;
     uint64_t tasks_total;             // tasks over all rounds
+    uint64_t side_keys;               // in-place rounds: side-buffer keys of the next round
     LiveCounts cur;                   // graph mode: the running round's sizes
 };
 
@@ -282,6 +331,25 @@ hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_c
                           const double* d_models, const uint64_t* d_pos, const uint8_t* d_skip,
                           const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, uint32_t max_leaves,
                           uint32_t flags, const LiveCounts* live, hipStream_t st);
+// In-place round (LS_FLAG_INPLACE): fragments written back into the chunks
+// (cnt: keys, pcnt: partial keys per (bucket, chunk); fullb: full blocks per
+// bucket, cleared by the caller; tags: the bucket of every block slot;
+// side: ip_side_keys(chunk, fanout) keys per chunk of a task from its
+// side_off), the plan of each
+// bucket's slots, the block permutation and the gather of the rest.
+hipError_t launch_ip_frag(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
+                          const double* d_models, uint32_t* d_cnt, uint32_t* d_pcnt, uint32_t* d_fullb,
+                          uint64_t* d_bstat, uint16_t* d_tags, uint64_t* d_side, uint32_t max_fanout,
+                          uint32_t max_leaves, uint32_t flags, hipStream_t st);
+size_t ip_frag_lds_bytes(uint32_t fanout, uint32_t leaves);
+hipError_t launch_ip_plan(const Task* d_tasks, uint32_t ntasks, uint64_t nbuckets, const uint64_t* d_pos,
+                          const uint32_t* d_fullb, IpBucket* d_bk, hipStream_t st);
+hipError_t launch_ip_permute(const Task* d_tasks, uint32_t ntasks, uint64_t nbuckets, uint64_t gslots,
+                             IpBucket* d_bk, const uint16_t* d_tags, uint32_t* d_done, uint64_t* d_ovf,
+                             uint32_t epoch, RoundCtl* d_ctl, hipStream_t st);
+hipError_t launch_ip_gather(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
+                            uint64_t nbuckets, const uint32_t* d_pcnt, const uint64_t* d_ppos, const IpBucket* d_bk,
+                            const uint64_t* d_side, const uint64_t* d_ovf, hipStream_t st);
 // Finishing kernels.  gctl (graph mode, may be null): ngroups / nfill are
 // upper bounds, the real counts are read from gctl, and nothing is done
 // while gctl->ntasks says partition rounds are still pending or after an

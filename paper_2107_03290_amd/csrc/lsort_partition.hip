@@ -6,16 +6,6 @@
 
 namespace lsort {
 
-__device__ __forceinline__ uint32_t find_task(const Task* tasks, uint32_t ntasks, uint32_t chunk)
-{
-    uint32_t lo = 0, hi = ntasks;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (tasks[mid].chunk0 <= chunk) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 __global__ void k_round_init(uint64_t* bstat, uint64_t nbuckets, RoundCtl* ctl, bool snapshot)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -276,7 +266,7 @@ constexpr int32_t kNone = 0x7fffffff;
 // 1024): chunk size, each task's chunk / bucket / count-matrix offsets, and a
 // training job (sample size, leaves, table offsets) for every task that
 // needs a local model.  The host only reads the totals back.
-constexpr uint32_t kLayoutQ = 9;
+constexpr uint32_t kLayoutQ = 10;
 
 __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& lp, RoundCtl* ctl,
                               RoundCtl* host_ctl)
@@ -323,12 +313,18 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
     // a large round scatters in wide tiles when its fanouts leave room in LDS
     const uint32_t tile =
         lp.tile_wide && nkeys >= lp.wide_keys && s_maxf <= lp.wide_max_fanout ? lp.tile_wide : lp.tile;
-    // at most kTargetChunks chunks; a small round gets about one chunk per
-    // CU, of one to four tiles
-    uint64_t chunk = (nkeys + kTargetChunks - 1) / kTargetChunks;
+    // at most lp.target_chunks chunks; a small round gets about one chunk
+    // per CU, of one to four tiles
+    uint64_t chunk = (nkeys + lp.target_chunks - 1) / lp.target_chunks;
     uint64_t small = (nkeys + kSmallRoundChunks - 1) / kSmallRoundChunks;
     small = small < tile ? tile : (small > 4ull * tile ? 4ull * tile : small);
     chunk = chunk > small ? chunk : small;
+    // in-place rounds: chunks of at least kIpChunkBlocks x fanout blocks, so
+    // that the open fragments at their ends stay a small fraction of the keys
+    if (lp.inplace) {
+        const uint64_t least = kIpChunkBlocks * s_maxf * kIpBlock;
+        chunk = chunk > least ? chunk : least;
+    }
     chunk = (chunk + tile - 1) / tile * tile;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     uint32_t my_maxl = 1;
@@ -353,19 +349,27 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
             // needs m/L copies), at most the caller's leaves
             const uint64_t want_l = m / 8 ? m / 8 : 1;
             L = (uint32_t)(want_l < lp.leaves ? want_l : lp.leaves);
+            // in-place rounds split many small ranges with small fanouts:
+            // their models get 8 leaves per bucket
+            if (lp.inplace)
+                L = min(L, max(kIpMinLeaves, 8u * T.fanout));
             my_maxl = max(my_maxl, L);
             my_maxm = max(my_maxm, (unsigned long long)m);
         }
         const uint64_t nch = valid ? (T.n + chunk - 1) / chunk : 0;
+        // a job whose sample fits one LDS run trains in one workgroup and
+        // takes no room in the sample buffers and leaf tables
+        const bool sampled = local && m > kSampleBlock;
         uint64_t q[kLayoutQ] = {nch,
                                 valid ? T.fanout : 0u,
                                 valid ? (uint64_t)T.fanout * nch : 0u,
                                 valid ? T.n : 0u,
                                 local ? 1u : 0u,
-                                m,
-                                L,
+                                sampled ? m : 0u,
+                                sampled ? L : 0u,
                                 local ? model_doubles(L) : 0u,
-                                local ? (m + kSampleBlock - 1) / kSampleBlock : 0u};
+                                sampled ? (m + kSampleBlock - 1) / kSampleBlock : 0u,
+                                lp.inplace && valid ? nch * ip_side_keys(chunk, T.fanout) : 0u};
         uint64_t x[kLayoutQ];
 #pragma unroll
         for (uint32_t j = 0; j < kLayoutQ; ++j) {
@@ -400,6 +404,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
             T.bucket_off = off[1];
             T.cnt_off = off[2];
             T.cnt_base = off[3];
+            T.side_off = off[9];
             if (local) {
                 T.leaves = L;
                 T.model = lp.model_base + off[7];
@@ -415,7 +420,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
                 J.leaves = L;
                 J.dtype = T.dtype;
                 J.block0 = (uint32_t)off[8];
-                J.nblocks = (uint32_t)((m + kSampleBlock - 1) / kSampleBlock);
+                J.nblocks = sampled ? (uint32_t)((m + kSampleBlock - 1) / kSampleBlock) : 0u;
                 jobs[off[4]] = J;
             }
             tasks[i] = T;
@@ -452,6 +457,7 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
         ctl->leafs = carry[6];
         ctl->models = carry[7];
         ctl->blocks = (uint32_t)carry[8];
+        ctl->side_keys = carry[9];
         ctl->max_fanout = s_maxf;
         ctl->max_leaves = s_maxl;
         ctl->max_level = s_maxlev;
@@ -676,7 +682,8 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
             const uint64_t lo = bstat[2 * ((uint64_t)T.bucket_off + b)];
             const uint64_t hi = bstat[2 * ((uint64_t)T.bucket_off + b) + 1];
             const bool stalled = noprog || (T.kind == kLocal && sz > T.n - T.n / 8u);
-            const uint32_t fc = child_fanout(sz, thresh, param_fanout);
+            const uint32_t fc0 = child_fanout(sz, thresh, param_fanout);
+            const uint32_t fc = lp.inplace ? ip_fanout(sz, fc0) : fc0;
             if (T.kind == kGlobal) {
                 // Alg. 2 level 1: the array's model again, f1 sub-buckets of bucket b
                 C.kind = kGlobalL1;

@@ -408,6 +408,8 @@ __global__ __launch_bounds__(256) void k_train_fit(const ModelJob* jobs, const u
     __shared__ int32_t ws32[17];
     __shared__ uint64_t s_lo, s_hi, s_run0;
     const ModelJob J = jobs[blockIdx.x];
+    if (J.m <= kSampleBlock)
+        return;     // trained in LDS by k_train_small
     const uint32_t L = J.leaves;
     const uint64_t* S = sorted + J.sample_off;
     if (threadIdx.x == 0) {
@@ -475,6 +477,8 @@ __global__ __launch_bounds__(256) void k_train_small(const ModelJob* jobs, doubl
     __shared__ uint32_t s_nf[2];
     __shared__ int32_t ws32[17];
     const ModelJob J = jobs[blockIdx.x];
+    if (J.m > kSampleBlock)
+        return;     // trained from the sample buffers
     const uint32_t n = (uint32_t)J.m;
     const uint32_t L = J.leaves;
     if (threadIdx.x == 0)
@@ -545,12 +549,13 @@ hipError_t launch_train(const ModelJob* d_jobs, uint32_t njobs, uint32_t total_b
                         uint64_t* d_first, uint64_t* d_nf, double* d_models, const LiveCounts* live,
                         hipStream_t st)
 {
-    if (!njobs || !total_blocks || !total)
+    if (!njobs)
         return hipSuccess;
-    if (max_sample <= kSampleBlock) {
-        k_train_small<<<njobs, 256, kSmallTrainLds, st>>>(d_jobs, d_models, live);
+    // jobs of at most kSampleBlock sample keys train in one workgroup each;
+    // the larger ones (nonzero sampling blocks) from the sample buffers
+    k_train_small<<<njobs, 256, kSmallTrainLds, st>>>(d_jobs, d_models, live);
+    if (max_sample <= kSampleBlock || !total_blocks || !total)
         return hipGetLastError();
-    }
     k_train_runs<<<total_blocks, 256, (size_t)base_pad(kSampleBlock) * 8, st>>>(d_jobs, njobs, d_sample, d_nf,
                                                                                  live);
     uint64_t* src = d_sample;

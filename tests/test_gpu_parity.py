@@ -170,13 +170,27 @@ def test_wide_tile_rounds_match_the_definition(S):
         assert np.array_equal(got, want)
 
 
-def test_tile_that_does_not_fit_is_rejected(S):
-    # 8192-key tiles with 4096 buckets need more LDS than one workgroup has
+def test_tile_that_does_not_fit_shrinks(S):
+    # 8192- and 4096-key tiles with 4096 buckets and the 1024-leaf model need
+    # more LDS than one workgroup has: the tile is halved until it fits
+    a = inputs("zipf", 3_000_000, 12)
+    for kw in (dict(tile=8192, fanout=4096), dict(tile=4096, fanout=4096, base_threshold=4096)):
+        assert np.array_equal(gpu_sort(S, a, ls.params(**kw)), expected_sorted(a))
     t = torch.zeros(10, dtype=torch.float64, device="cuda:0")
     with pytest.raises(ls.LsortError):
-        S.sort_(t, ls.params(tile=8192, fanout=4096))
-    with pytest.raises(ls.LsortError):
         S.sort_(t, ls.params(tile=3000))
+
+
+def test_device_bytes_and_trim(S):
+    # the context keeps its work buffers (a key-sized scratch among them)
+    # between sorts; trim frees them and the next sort allocates them again
+    a = inputs("uniform", 1_000_000, 13)
+    assert np.array_equal(gpu_sort(S, a), expected_sorted(a))
+    assert S.device_bytes() >= a.size * 8
+    S.trim()
+    assert S.device_bytes() == 0
+    assert np.array_equal(gpu_sort(S, a), expected_sorted(a))
+    assert S.device_bytes() >= a.size * 8
 
 
 def test_profile_all_classes_and_one_class(S):
