@@ -526,6 +526,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="keys the CPU oracle sorts (0: the whole array)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verify", action="store_true", help="check the sorted output against numpy")
+    ap.add_argument("--inplace", action="store_true",
+                    help="in-place partition rounds (fragments and block permutation; no key-sized scratch)")
     ap.add_argument("--segments", type=int, default=10_000, help="arrays of the segments workload")
     ap.add_argument("--requests", type=int, default=400, help="requests of the served workload")
     ap.add_argument("--sweep-max-n", type=int, default=0, help="sweep workload: skip points above this size")
@@ -573,19 +575,28 @@ def main():
     if args.sample_cap >= 0:
         kw["sample_cap"] = args.sample_cap
     stream = torch.cuda.current_stream(dev)
+    extra = ls.FLAG_INPLACE if args.inplace else 0
 
     def run(flags):
         work[0].copy_(pristine)
-        S.sort_(work[0], ls.params(flags=flags, **kw))
+        S.sort_(work[0], ls.params(flags=flags | extra, **kw))
 
     breakdown, gbps, dom, flags = profiled_warmup(S, ls, run, Wm)
-    p = ls.params(flags=flags, **kw)
+    p = ls.params(flags=flags | extra, **kw)
     if args.verify:
-        from tests.helpers import expected_sorted
-        got = work[0].view(torch.int64).cpu().numpy().view(np.uint64)
-        if not np.array_equal(got, expected_sorted(keys)):
+        # against torch.sort on the device (the definition of the result,
+        # computed without the library)
+        raw = pristine.view(torch.int64)
+        if keys.dtype == np.uint64:
+            sign = torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
+            want = torch.sort(raw ^ sign)[0] ^ sign
+        else:
+            want = library_sorted_words(raw, torch)
+        if not torch.equal(work[0].view(torch.int64), want):
             raise SystemExit("verification failed")
-        print("verified against numpy", file=sys.stderr, flush=True)
+        del want
+        torch.cuda.empty_cache()
+        print("verified against torch.sort", file=sys.stderr, flush=True)
     for w in work:
         w.copy_(pristine)
     torch.cuda.synchronize()
@@ -630,7 +641,15 @@ def main():
                             "steps time the dominant class (%s) only" % (PROFILED_STEPS, dom),
         "pipeline": stats[-1],
         "wall_s_timed": wall,
+        "context_device_bytes": S.device_bytes(),
     }
+    if args.inplace:
+        # the in-place rounds time the fragment pass in the histogram's class
+        # and the block permutation with the gather in the scatter's
+        line["config"]["partition"] = "in-place (Alg. 1 fragments, then block permutation and gather)"
+        line["config"]["class_names"] = {"hist": "fragments (k_ip_frag)",
+                                         "scatter": "plan + permutation + gather (k_ip_plan/permute/gather)"}
+        line["extra_device_frac"] = S.device_bytes() / (n * 8.0)
     if not args.no_cpu_baseline:
         take = min(args.cpu_sample, n) if args.cpu_sample > 0 else n
         line["cpu_baseline"] = cpu_baseline(keys, take)

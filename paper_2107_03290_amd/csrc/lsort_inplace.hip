@@ -392,27 +392,17 @@ __device__ __forceinline__ uint64_t ip_claim_read(unsigned long long* p)
     return ip_uni64(old);
 }
 
-// Lane 0: claim bucket p's next free slot (w += 1), unless all of its slots
-// [.., dend) are taken; w never passes dend, so readers still reach the
-// slots above it.  Returns the (w, r) word before the claim, or ~0 when full.
-__device__ __forceinline__ uint64_t ip_claim_write(unsigned long long* p, uint32_t dend)
+// Lane 0: claim bucket p's next free slot (w += 1).  Returns the (w, r) word
+// before the claim; w >= dend there means the bucket's block that does not
+// fit (at most one per bucket, so w ends at dend + 1 or below).  One atomic
+// add per claim: a compare-and-swap loop would retry under the contention
+// of thousands of waves writing into few buckets.
+__device__ __forceinline__ uint64_t ip_claim_write(unsigned long long* p)
 {
-    uint64_t res = 0;
-    if (threadIdx.x % 64 == 0) {
-        unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (;;) {
-            if ((uint32_t)cur >= dend) {
-                cur = ~0ull;
-                break;
-            }
-            const unsigned long long prev = atomicCAS(p, cur, cur + 1ull);
-            if (prev == cur)
-                break;
-            cur = prev;
-        }
-        res = cur;
-    }
-    return ip_uni64(res);
+    uint64_t old = 0;
+    if (threadIdx.x % 64 == 0)
+        old = atomicAdd(p, 1ull);
+    return ip_uni64(old);
 }
 
 // Lane 0: wait (bounded) until the reader that claimed a slot has its block in
@@ -471,11 +461,13 @@ __global__ __launch_bounds__(256) void k_ip_permute(const Task* tasks, uint32_t 
         const uint64_t soff = ip_uni64(ip_slot_off(tasks[ti], ti));
         const uint64_t boff = ip_uni64(tasks[ti].bucket_off);
         const gptr<uint64_t> base = as_global(uni_keys(tasks[ti]));
+        // slots at or above dend are never written: they are read whatever w is
+        const int32_t rd_end = (int32_t)ip_uni32(bk[gb].dend);
         bool more = true;
         while (more) {
             const uint64_t old = ip_claim_read((unsigned long long*)&bk[gb].ptr);
             const int32_t w_old = (int32_t)(uint32_t)old, r_old = (int32_t)(uint32_t)(old >> 32);
-            if (r_old < w_old) {
+            if (r_old < min(w_old, rd_end)) {
                 more = false;
             } else {
                 const uint64_t s = (uint32_t)r_old;
@@ -487,8 +479,8 @@ __global__ __launch_bounds__(256) void k_ip_permute(const Task* tasks, uint32_t 
                 uint64_t d = boff + tg0;
                 bool carrying = tg0 != kIpEmpty;
                 while (carrying) {
-                    const uint64_t o2 = ip_claim_write((unsigned long long*)&bk[d].ptr, ip_uni32(bk[d].dend));
-                    if (o2 == ~0ull) {
+                    const uint64_t o2 = ip_claim_write((unsigned long long*)&bk[d].ptr);
+                    if ((uint32_t)o2 >= ip_uni32(bk[d].dend)) {
                         // the bucket's block that does not fit
                         ovf[d * kIpBlock + lane] = key;
                         carrying = false;
