@@ -240,104 +240,131 @@ def bench_served(args, torch, ls):
     duplicate ratio U(0, 0.99)) served by the continuous-batching server
     against one-request-at-a-time plain sorting, first as a burst (all
     requests queued at once: throughput), then with Poisson arrivals at 80%
-    of the plain rate (latency).  Every served result must equal the plain
-    one."""
+    of the plain rate (latency).
+
+    Request i sorts a copy of distinct request i mod D (D generated ones)
+    made in work slot i mod Q just before it is submitted (plain: just before
+    it is sorted), so the stream can be longer than device memory holds; a
+    slot is reused once its request completes.  The copy is part of every
+    request on both paths.  Every served result is compared with the plain
+    result of the same request in an untimed pass."""
     import threading
     import workloads as W
     from concurrent.futures import ThreadPoolExecutor
-    R = args.requests
+    R, D, Q = args.requests, min(args.requests, args.distinct), min(args.requests, args.ring)
     spec = W.request_spec()
     t0 = time.perf_counter()
     with ThreadPoolExecutor(16) as ex:
-        reqs = list(ex.map(lambda i: W.request_keys(spec, i), range(R)))
-    total = int(sum(a.size for a in reqs))
-    print("served: %d requests, %d keys generated in %.1f s" % (R, total, time.perf_counter() - t0),
-          file=sys.stderr, flush=True)
+        reqs = list(ex.map(lambda i: W.request_keys(spec, i), range(D)))
+    sizes = [reqs[i % D].size for i in range(R)]
+    total = int(sum(sizes))
+    print("served: %d requests over %d distinct ones, %d keys in all (generated in %.1f s)" %
+          (R, D, total, time.perf_counter() - t0), file=sys.stderr, flush=True)
     # graph mode (LS_FLAG_GRAPH): requests and batches of up to 2^22 keys run
     # as replays of captured graphs, on the plain path and in the server
     gp = ls.params(flags=ls.FLAG_GRAPH if args.graph == "on" else 0)
     pristine = [to_device(a, torch) for a in reqs]
-    work = [torch.empty_like(t) for t in pristine]
-    ref = [torch.empty_like(t) for t in pristine]
+    biggest = max(a.size for a in reqs)
+    slots = [torch.empty(biggest, dtype=torch.int64, device="cuda:0") for _ in range(Q)]
     S = ls.Sorter(0)
 
-    def restore(dst):
-        for d, p in zip(dst, pristine):
-            d.copy_(p)
-        torch.cuda.synchronize()
+    def slot_view(i):
+        src = pristine[i % D]
+        v = slots[i % Q][:src.numel()]
+        return src, (v.view(torch.float64) if src.dtype == torch.float64 else v)
 
-    # warm-up both paths (buffers grow once)
-    restore(ref)
-    for t in ref[:8]:
+    # plain results (the reference of every request) and warm-up
+    ref = []
+    for src in pristine:
+        t = src.clone()
         S.sort_(t, gp)
+        ref.append(t)
     torch.cuda.synchronize()
 
     def run_plain(arrival):
-        restore(ref)
         lat = []
         start = time.perf_counter()
-        for t, a in zip(ref, arrival):
+        for i in range(R):
             now = time.perf_counter() - start
-            if now < a:
-                time.sleep(a - now)
-            S.sort_(t, gp)
+            if now < arrival[i]:
+                time.sleep(arrival[i] - now)
+            src, dst = slot_view(i)
+            dst.copy_(src)
+            S.sort_(dst, gp)
             torch.cuda.synchronize()
-            lat.append(time.perf_counter() - start - a)
+            lat.append(time.perf_counter() - start - arrival[i])
         return time.perf_counter() - start, lat
 
-    def run_served(arrival):
-        restore(work)
+    def run_served(arrival, check=False):
         srv = ls.Server(0, hbm_budget=args.budget_gb << 30, max_inflight=args.inflight, p=gp)
-        tickets = [None] * R
+        tickets, lat, bad = [None] * R, [0.0] * R, []
         sub_t = [0.0] * R
         start = time.perf_counter()
+        stream = torch.cuda.Stream()
+
+        def finish(j):
+            lat[j] = sub_t[j] - arrival[j] + srv.wait(tickets[j])
+            if check:
+                _, out = slot_view(j)
+                if not torch.equal(out.view(torch.int64), ref[j % D].view(torch.int64)):
+                    bad.append(j)
 
         def submitter():
-            for i, a in enumerate(arrival):
-                now = time.perf_counter() - start
-                if now < a:
-                    time.sleep(a - now)
-                sub_t[i] = time.perf_counter() - start
-                tickets[i] = srv.submit(work[i])
+            with torch.cuda.stream(stream):
+                for i in range(R):
+                    if i >= Q:
+                        finish(i - Q)             # its slot is needed again
+                    now = time.perf_counter() - start
+                    if now < arrival[i]:
+                        time.sleep(arrival[i] - now)
+                    sub_t[i] = time.perf_counter() - start
+                    src, dst = slot_view(i)
+                    dst.copy_(src)
+                    stream.synchronize()
+                    tickets[i] = srv.submit(dst)
+                for j in range(max(0, R - Q), R):
+                    finish(j)
 
         th = threading.Thread(target=submitter)
         th.start()
-        th.join() if arrival[-1] == 0 else None
-        lat = []
-        for i in range(R):
-            while tickets[i] is None:
-                time.sleep(1e-4)
-            srv_lat = srv.wait(tickets[i])
-            lat.append(sub_t[i] - arrival[i] + srv_lat)
         th.join()
         wall = time.perf_counter() - start
         st = srv.stats()
         srv.close()
+        if bad:
+            raise SystemExit("served and plain results differ for requests %s" % bad[:10])
         return wall, lat, st
 
     burst = [0.0] * R
     wp, lp = run_plain(burst)
     ws, lsv, st_b = run_served(burst)
-    same_b = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(work, ref))
     mu = R / wp                                # plain requests per second
     lam = 0.8 * mu
     arrival = list(np.asarray(spec.arrival_s[:R]) * (1000.0 / lam))   # spec drawn at 1000 req/s
     arrival = [a - arrival[0] for a in arrival]
     wp2, lp2 = run_plain(arrival)
     ws2, ls2, st_p = run_served(arrival)
-    same_p = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(work, ref))
-    if not (same_b and same_p):
-        raise SystemExit("served and plain results differ")
+    run_served(burst, check=True)              # untimed: every served result equals the plain one
+    for j in range(min(D, 8)):                 # and the plain results equal the definition
+        raw = pristine[j].view(torch.int64)
+        if pristine[j].dtype == torch.float64:
+            want = library_sorted_words(raw, torch)
+        else:
+            sign = torch.tensor(-(1 << 63), dtype=torch.int64, device=raw.device)
+            want = torch.sort(raw ^ sign)[0] ^ sign
+        if not torch.equal(ref[j].view(torch.int64), want):
+            raise SystemExit("plain result %d differs from torch.sort" % j)
     line = {
         "metric": METRIC, "value": total / ws, "unit": "keys/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": ws * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+u64", "data": "synthetic (seeded generator; no dataset)",
-        "config": {"workload": "served_%d_requests" % R, "keys": total, "budget_gb": args.budget_gb,
-                   "max_inflight": args.inflight, "graph": args.graph == "on"},
+        "config": {"workload": "served_%d_requests" % R, "distinct_requests": D, "work_slots": Q,
+                   "keys": total, "budget_gb": args.budget_gb, "max_inflight": args.inflight,
+                   "graph": args.graph == "on"},
         "burst": {"served_keys_per_s": total / ws, "plain_keys_per_s": total / wp,
                   "served_p50_s": pct(lsv, 50), "served_p99_s": pct(lsv, 99),
                   "plain_p50_s": pct(lp, 50), "plain_p99_s": pct(lp, 99), "batches": st_b["batches"],
-                  "peak_admitted_bytes": st_b["peak_bytes"]},
+                  "peak_accounted_bytes": st_b["peak_bytes"]},
         "poisson": {"rate_per_s": lam, "plain_rate_per_s": mu,
                     "served_keys_per_s": total / ws2, "plain_keys_per_s": total / wp2,
                     "served_p50_s": pct(ls2, 50), "served_p99_s": pct(ls2, 99),
@@ -529,10 +556,12 @@ def main():
     ap.add_argument("--inplace", action="store_true",
                     help="in-place partition rounds (fragments and block permutation; no key-sized scratch)")
     ap.add_argument("--segments", type=int, default=10_000, help="arrays of the segments workload")
-    ap.add_argument("--requests", type=int, default=400, help="requests of the served workload")
+    ap.add_argument("--requests", type=int, default=5000, help="requests of the served workload")
+    ap.add_argument("--distinct", type=int, default=256, help="served workload: distinct requests generated")
+    ap.add_argument("--ring", type=int, default=64, help="served workload: work slots (requests outstanding)")
     ap.add_argument("--sweep-max-n", type=int, default=0, help="sweep workload: skip points above this size")
     ap.add_argument("--budget-gb", type=int, default=200)
-    ap.add_argument("--inflight", type=int, default=1, help="served workload: batches in flight at once")
+    ap.add_argument("--inflight", type=int, default=2, help="served workload: batches in flight at once")
     ap.add_argument("--graph", choices=("on", "off"), default="off",
                     help="served workload: run requests and batches of up to 2^22 keys as graph replays")
     args = ap.parse_args()

@@ -100,12 +100,15 @@ typedef struct ls_ctx ls_ctx;
 
 /* Create a context on HIP device `device` (the device becomes current). */
 ls_status ls_create(ls_ctx** out, int device);
+/* Wait for the context's queued work (not the whole device's), then free it. */
 ls_status ls_destroy(ls_ctx* ctx);
 
 /* Fill *p with the defaults. */
 void ls_default_params(ls_params* p);
 
-/* Device bytes of scratch a sort of n keys needs (upper estimate). */
+/* Device bytes of work buffers a sort of n keys needs (an estimate: the
+ * scratch keys, or about n B in place with LS_FLAG_INPLACE, plus round
+ * tables, output lists and training samples).  ctx may be NULL. */
 ls_status ls_workspace_size(ls_ctx* ctx, ls_dtype dtype, size_t n, const ls_params* p, size_t* bytes);
 
 /* Allocate scratch for sorts of up to n keys ahead of time. */
@@ -199,8 +202,8 @@ ls_status ls_autotune(ls_ctx* ctx, const ls_array* h_arrays, size_t count, ls_st
                       const ls_params* base, uint32_t reps, ls_params* best, ls_tune_result* results,
                       size_t cap, size_t* n_results);
 
-/* Wait for the context's last sort and report device status bits
- * (LS_DEV_*); device_status may be NULL. */
+/* Wait for the context's last sort (its queued work only) and report device
+ * status bits (LS_DEV_*); device_status may be NULL. */
 ls_status ls_sync(ls_ctx* ctx, uint32_t* device_status);
 
 /* Counters of the last completed sort (filled by ls_sync):
@@ -249,18 +252,26 @@ ls_status ls_stage_hist(ls_ctx* ctx, ls_dtype dtype, const void* d_keys, size_t 
 
 typedef struct ls_server ls_server;
 
-/* Start a server on `device` that admits requests while the device memory
- * they need (keys already resident + the library's scratch) stays within
- * hbm_budget_bytes, batches the admitted ones into segmented sorts, and
- * keeps up to max_inflight batches in flight on separate streams.  p may be
- * NULL (the defaults).  With LS_FLAG_GRAPH in p->flags, batches of at most
- * 2^22 keys run as replays of graphs each worker captures per size class. */
+/* Start a server on `device` with max_inflight workers, each with its own
+ * context and stream, so that up to max_inflight batches run on the device
+ * at once.  A free worker batches queued requests into one segmented sort.
+ * Admission keeps the accounted device memory within hbm_budget_bytes:
+ * the keys of the requests being sorted (n x 8 B each, the caller's
+ * buffers), plus every worker's context.  An idle context counts what it
+ * holds (ls_device_bytes).  A busy one counts that plus a bound on what its
+ * batch can add (1.5 x ls_workspace_size, since a buffer grows by at least
+ * half of itself).  A worker whose own retained buffers keep the oldest
+ * request out frees them (ls_trim) first.  p may be NULL (the defaults);
+ * with LS_FLAG_INPLACE the batches need about n B instead of n x 8 B of
+ * scratch.  With LS_FLAG_GRAPH, batches of at most 2^22 keys run as replays
+ * of graphs that each worker captures per size class. */
 ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
                            uint32_t max_inflight, const ls_params* p);
 
 /* Queue a request: sort d_keys (device, n keys of dtype) in place.  Returns
- * immediately with a ticket.  A request that can never fit the budget is
- * rejected with LS_ERR_BUDGET; one that fits later waits in the queue. */
+ * immediately with a ticket.  A request that can never fit the budget (its
+ * keys and its batch bound alone exceed it) is rejected with LS_ERR_BUDGET;
+ * one that fits later waits in the queue. */
 ls_status ls_server_submit(ls_server* s, ls_dtype dtype, void* d_keys, size_t n, uint64_t* ticket);
 
 /* Wait for a ticket (timeout_ms < 0: forever).  latency_s receives the time
@@ -268,7 +279,8 @@ ls_status ls_server_submit(ls_server* s, ls_dtype dtype, void* d_keys, size_t n,
 ls_status ls_server_wait(ls_server* s, uint64_t ticket, int timeout_ms, double* latency_s);
 
 /* Server counters: [0] submitted, [1] completed, [2] batches, [3] peak
- * admitted bytes, [4] currently admitted bytes, [5] queued requests. */
+ * accounted bytes, [4] accounted bytes now (keys being sorted + what the
+ * workers' contexts hold or have reserved), [5] queued requests. */
 ls_status ls_server_stats(ls_server* s, uint64_t* out6);
 
 /* Copy the message of the latest failed batch (empty if none) into buf

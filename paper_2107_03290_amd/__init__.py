@@ -433,7 +433,7 @@ class Server:
     def stats(self) -> dict:
         a = (ctypes.c_uint64 * 6)()
         lib().ls_server_stats(self._s, a)
-        return dict(zip(("submitted", "completed", "batches", "peak_bytes", "admitted_bytes", "queued"),
+        return dict(zip(("submitted", "completed", "batches", "peak_bytes", "accounted_bytes", "queued"),
                         [int(x) for x in a]))
 
     def close(self):

@@ -125,6 +125,10 @@ struct ls_ctx {
     // finish: the base-case size classes run side by side
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+    // the end of the context's last queued sort on the caller's stream:
+    // sync, trim and destroy wait for this context's work, not the device's
+    hipEvent_t ev_done = nullptr;
+    bool done_pending = false;
     std::vector<GraphEntry> graphs;
     std::vector<RoundsHint> hints;
     // no-allocation sorts (ls_sort_noalloc): this device's static array, and
@@ -1344,6 +1348,38 @@ ls_status run_pipeline(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, co
     return conclude(C, arrays, st, P, msd_only);
 }
 
+// Record the end of a sort's work on the caller's stream.
+void mark_done(ls_ctx* C, hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!C->ev_done || hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone ||
+        hipEventRecord(C->ev_done, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    C->done_pending = true;
+}
+
+// Wait until the context's queued work (its last sort, its own streams) ends.
+ls_status wait_ctx(ls_ctx* C)
+{
+    if (C->done_pending)
+        HIPCHECK(C, hipEventSynchronize(C->ev_done));
+    C->done_pending = false;
+    for (hipStream_t s : {C->side[0], C->side[1], C->cap_stream})
+        if (s)
+            HIPCHECK(C, hipStreamSynchronize(s));
+    return LS_OK;
+}
+
+ls_status run_pipeline_marked(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const Params& P,
+                              bool msd_only)
+{
+    const ls_status s = run_pipeline(C, arrays, st, P, msd_only);
+    mark_done(C, st);
+    return s;
+}
+
 ls_status sort_arrays(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const ls_params* p)
 {
     GateUse gate;
@@ -1360,7 +1396,7 @@ ls_status sort_arrays(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, con
     HIPCHECK(C, hipSetDevice(C->device));
     C->dev_status = 0;
     std::memset(C->stats, 0, sizeof C->stats);
-    return run_pipeline(C, arrays, st, P, false);
+    return run_pipeline_marked(C, arrays, st, P, false);
 }
 
 }  // namespace
@@ -1417,12 +1453,15 @@ ls_status ls_create(ls_ctx** out, int device)
     // the no-allocation sort's static array on this device (the device is
     // current), and pinned staging for its round-0 lists
     if (noalloc_setup(device, &C->na_base, &C->na_bytes) != hipSuccess ||
+        hipEventCreateWithFlags(&C->ev_done, hipEventDisableTiming) != hipSuccess ||
         ensure_pinned(C, C->estage, 65536, nullptr) != LS_OK) {
         (void)hipGetLastError();
         (void)hipHostFree(C->h_ctl);
         (void)hipHostFree(C->h_flag);
         if (C->estage.p)
             (void)hipHostFree(C->estage.p);
+        if (C->ev_done)
+            (void)hipEventDestroy(C->ev_done);
         delete C;
         return LS_ERR_HIP;
     }
@@ -1436,7 +1475,8 @@ ls_status ls_destroy(ls_ctx* C)
     if (!C)
         return LS_ERR_INVALID;
     (void)hipSetDevice(C->device);
-    (void)hipDeviceSynchronize();
+    (void)wait_ctx(C);
+    (void)hipGetLastError();
     for (DevBuf* b : ctx_bufs(C))
         if (b->p)
             (void)hipFree(b->p);
@@ -1461,21 +1501,28 @@ ls_status ls_destroy(ls_ctx* C)
     }
     if (C->ev_fork)
         (void)hipEventDestroy(C->ev_fork);
+    if (C->ev_done)
+        (void)hipEventDestroy(C->ev_done);
     delete C;
     return LS_OK;
 }
 
 ls_status ls_workspace_size(ls_ctx* C, ls_dtype dtype, size_t n, const ls_params* p, size_t* bytes)
 {
-    if (!C || !bytes || (dtype != LS_F64 && dtype != LS_U64))
+    if (!bytes || (dtype != LS_F64 && dtype != LS_U64))
         return LS_ERR_INVALID;
+    ls_ctx scratch_ctx;                 // parameter checks only (no HIP call, no LDS limit)
+    scratch_ctx.lds_limit = ~(size_t)0 >> 1;
     Params P;
-    TRY(resolve(C, p, P));
+    TRY(resolve(C ? C : &scratch_ctx, p, P));
     size_t chunks = kTargetChunks + 64;
     size_t tables = (size_t)P.fanout * chunks * 12 + (size_t)P.fanout * 64 + model_doubles(P.leaves) * 8 * 4;
     size_t lists = (n / 2 + P.fanout) * (sizeof(Group) + sizeof(Fill)) / 8;
-    // scratch keys, round tables, output lists, training sample
-    *bytes = n * 8 + tables + lists + (2 * std::min<size_t>(n / 50 + 4096, kDefaultSampleCap + 4096)) * 8;
+    // scratch keys (in place: side buffer, overflow blocks, tags and flags,
+    // each a small fraction of the keys), round tables, output lists,
+    // training sample
+    const size_t keys = (P.flags & LS_FLAG_INPLACE) ? n : n * 8;
+    *bytes = keys + tables + lists + (2 * std::min<size_t>(n / 50 + 4096, kDefaultSampleCap + 4096)) * 8;
     return LS_OK;
 }
 
@@ -1508,7 +1555,7 @@ ls_status ls_trim(ls_ctx* C)
     if (!C)
         return LS_ERR_INVALID;
     HIPCHECK(C, hipSetDevice(C->device));
-    HIPCHECK(C, hipDeviceSynchronize());
+    TRY(wait_ctx(C));
     drop_graphs(C, true);
     for (DevBuf* b : ctx_bufs(C)) {
         if (b->p)
@@ -1594,7 +1641,7 @@ ls_status ls_sort_noalloc(ls_ctx* C, ls_dtype dtype, void* d_keys, size_t n, ls_
         if (rc == LS_OK && launch_zero(t->p, t->cap, st) != hipSuccess)
             rc = fail(C, LS_ERR_HIP, "clearing the training tables failed");
     if (rc == LS_OK)
-        rc = run_pipeline(C, a, st, P, false);
+        rc = run_pipeline_marked(C, a, st, P, false);
     C->no_alloc = false;
     for (size_t i = 0; i < kCtxBufs; ++i)
         *bufs[i] = saved[i];
@@ -1759,7 +1806,7 @@ ls_status ls_sync(ls_ctx* C, uint32_t* device_status)
     if (!C)
         return LS_ERR_INVALID;
     HIPCHECK(C, hipSetDevice(C->device));
-    HIPCHECK(C, hipDeviceSynchronize());
+    TRY(wait_ctx(C));
     if (device_status)
         *device_status = C->dev_status;
     return LS_OK;

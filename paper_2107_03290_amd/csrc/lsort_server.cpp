@@ -2,15 +2,21 @@
 //
 // Requests (device buffers, sorted in place) wait in a FIFO queue.  Each of
 // `max_inflight` workers owns a library context and a HIP stream; when free
-// it admits queued requests in arrival order while the bytes they occupy on
-// the device (keys + the scratch the sort needs) stay within the budget, and
-// sorts them as one batch.  A batch's keys are capped relative to its oldest
-// request, so a small request does not wait for a large one batched with it;
-// a request over the cap stays queued for a later batch.  Requests that
-// arrive while other batches run are picked up by the next free worker, so
-// batches overlap on the GPU.  The admission stops at the first request the
-// budget cannot hold, and a request is only passed by later arrivals until it
-// is the oldest, so none is overtaken indefinitely.
+// it admits queued requests in arrival order while the accounted device
+// memory stays within the budget, and sorts them as one batch.  The account
+// holds the keys of the requests being sorted, what each idle worker's
+// context keeps (it reuses its buffers from batch to batch), and for a busy
+// worker that plus a bound on what its batch can add.  A worker whose own
+// kept buffers stand in the way of the oldest request frees them first.  A
+// batch's keys are capped relative to its oldest request, so a small request
+// does not wait for a large one batched with it; a request over the cap stays
+// queued for a later batch.  Requests that arrive while other batches run are
+// picked up by the next free worker, so batches overlap on the GPU; while
+// few requests wait, a request large enough to fill the device runs beside
+// small batches only, not beside another large one.  The
+// admission stops at the first request the budget cannot hold, and a request
+// is only passed by later arrivals until it is the oldest, so none is
+// overtaken indefinitely.
 #include "lsort.h"
 
 #include <hip/hip_runtime.h>
@@ -21,6 +27,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -43,7 +50,6 @@ struct Done {
     double latency_s;
 };
 
-constexpr uint64_t kBytesPerKey = 16;             // the keys plus their scratch
 // A batch holds at most min(limit, max(kBatchFloorKeys, kBatchGrowth x its
 // first request's keys)) keys, or its first request alone: batching pays for
 // many small (launch-bound) requests, while a small request batched with a
@@ -55,6 +61,14 @@ constexpr uint64_t kBacklogBatchKeys = 1ull << 29;
 constexpr size_t kBacklog = 8;
 constexpr uint64_t kBatchFloorKeys = 1ull << 22;
 constexpr uint64_t kBatchGrowth = 4;
+// Fixed part of a batch's bound (models, control blocks, smallest buffers).
+constexpr uint64_t kBoundFloor = 8ull << 20;
+// While at most kBacklog requests wait, a request of at least this many keys
+// (one that fills the device by itself) runs in no batch beside another
+// such batch: two of them side by side would each take about twice as long,
+// which is the latency of the largest requests, while small requests still
+// run beside it.
+constexpr uint64_t kLargeRequestKeys = 1ull << 23;
 
 }  // namespace
 
@@ -68,17 +82,59 @@ struct ls_server {
     std::unordered_map<uint64_t, Done> done;
     std::unordered_map<uint64_t, bool> pending;
     uint64_t next_ticket = 1;
-    uint64_t admitted = 0, peak = 0;
+    uint64_t keys_bytes = 0;           // keys of the requests being sorted
+    uint32_t large_running = 0;        // batches running with a request of >= kLargeRequestKeys
+    std::vector<uint64_t> held;        // per worker: its context's buffers (+ its batch's bound while busy)
+    uint64_t peak = 0;
     uint64_t n_submitted = 0, n_completed = 0, n_batches = 0;
     bool stopping = false;
     std::vector<std::thread> workers;
-    ls_status fatal = LS_OK;
     std::string last_error;   // message of the latest failed batch
 };
 
 namespace {
 
-void worker_main(ls_server* S)
+// Bound on the device memory a batch of `keys` keys can add to a context:
+// every buffer grows to at most 1.5 x what the batch needs (a buffer grows
+// by at least half of itself), plus the fixed part.
+uint64_t batch_bound(const ls_server* S, uint64_t keys)
+{
+    size_t need = 0;
+    if (ls_workspace_size(nullptr, LS_F64, keys, &S->params, &need) != LS_OK)
+        need = keys * 8;
+    return need + need / 2 + kBoundFloor;
+}
+
+uint64_t accounted(const ls_server* S)
+{
+    return S->keys_bytes + std::accumulate(S->held.begin(), S->held.end(), (uint64_t)0);
+}
+
+// Whether worker w can sort `keys` more keys now, with `own` bytes kept by
+// its context (the caller holds the lock).
+bool fits(const ls_server* S, uint32_t w, uint64_t keys, uint64_t own)
+{
+    const uint64_t others = accounted(S) - S->held[w];
+    return others + own + keys * 8 + batch_bound(S, keys) <= S->budget;
+}
+
+// Whether request r may be admitted now as far as the large-request rule is
+// concerned (the caller holds the lock).
+bool may_run(const ls_server* S, const Request& r)
+{
+    return S->queue.size() > kBacklog || S->large_running == 0 || r.n < kLargeRequestKeys;
+}
+
+// The oldest request a batch may start with now, or nullptr.
+const Request* lead(const ls_server* S)
+{
+    for (const Request& r : S->queue)
+        if (may_run(S, r))
+            return &r;
+    return nullptr;
+}
+
+void worker_main(ls_server* S, uint32_t w)
 {
     ls_ctx* ctx = nullptr;
     hipStream_t st = nullptr;
@@ -88,49 +144,74 @@ void worker_main(ls_server* S)
     std::vector<ls_array> arrays;
     for (;;) {
         batch.clear();
-        uint64_t bytes = 0;
+        uint64_t keys = 0;
+        bool trim = false, has_large = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
+            // wake to sort the oldest request, or to free this context's
+            // buffers when they alone keep it out
             S->cv_work.wait(lk, [&] {
-                if (S->stopping && S->queue.empty())
-                    return true;
                 if (S->queue.empty())
-                    return false;
-                return S->admitted + S->queue.front().n * kBytesPerKey <= S->budget;
+                    return S->stopping;
+                const Request* r = lead(S);
+                if (!r)
+                    return false;   // only large requests wait, behind a large batch
+                return fits(S, w, r->n, S->held[w]) || (S->held[w] > 0 && fits(S, w, r->n, 0));
             });
             if (S->queue.empty())
                 break;
-            // The oldest request leads; later ones join while they fit the
-            // batch's key cap, and admission stops at the first request the
-            // memory budget cannot hold.  A request skipped for the cap is
-            // only ever passed by later arrivals until it leads a batch.
-            const uint64_t limit = S->queue.size() > kBacklog ? kBacklogBatchKeys : kLatencyBatchKeys;
-            const uint64_t cap = std::min(limit, std::max(kBatchFloorKeys, kBatchGrowth * S->queue.front().n));
-            // (the first request is admitted whatever its size)
-            uint64_t keys = 0;
-            std::deque<Request> rest;
-            while (!S->queue.empty()) {
-                Request r = S->queue.front();
-                const uint64_t b = r.n * kBytesPerKey;
-                if (S->admitted + b > S->budget)
-                    break;
-                S->queue.pop_front();
-                if (!batch.empty() && keys + r.n > cap) {
-                    rest.push_back(r);
-                    continue;
+            const Request* first = lead(S);
+            if (!fits(S, w, first->n, S->held[w])) {
+                trim = true;
+            } else {
+                // The oldest request that may run leads; later ones join while
+                // they fit the batch's key cap, and admission stops at the
+                // first request the memory budget cannot hold.  A request
+                // skipped for the cap or the large-request rule is only ever
+                // passed by later arrivals until it leads a batch (a large one
+                // waits at most for the large batch running).
+                const uint64_t limit = S->queue.size() > kBacklog ? kBacklogBatchKeys : kLatencyBatchKeys;
+                const uint64_t cap = std::min(limit, std::max(kBatchFloorKeys, kBatchGrowth * first->n));
+                // (the first request is admitted whatever its size)
+                std::deque<Request> keep;   // what stays queued, in order
+                bool stop = false, large = false;
+                for (const Request& r : S->queue) {
+                    if (stop || !may_run(S, r)) {
+                        keep.push_back(r);
+                        continue;
+                    }
+                    if (!fits(S, w, keys + r.n, S->held[w])) {
+                        stop = true;
+                        keep.push_back(r);
+                        continue;
+                    }
+                    if (!batch.empty() && keys + r.n > cap) {
+                        keep.push_back(r);
+                        continue;
+                    }
+                    keys += r.n;
+                    large |= r.n >= kLargeRequestKeys;
+                    batch.push_back(r);
                 }
-                S->admitted += b;
-                bytes += b;
-                keys += r.n;
-                batch.push_back(r);
+                S->queue.swap(keep);
+                has_large = large;
+                S->large_running += large ? 1u : 0u;
+                S->keys_bytes += keys * 8;
+                S->held[w] += batch_bound(S, keys);
+                S->peak = std::max(S->peak, accounted(S));
+                S->n_batches++;
             }
-            // skipped requests go back in front, in their order
-            while (!rest.empty()) {
-                S->queue.push_front(rest.back());
-                rest.pop_back();
+        }
+        if (trim) {
+            size_t b = 0;
+            if (ctx && (ls_trim(ctx) != LS_OK || ls_device_bytes(ctx, &b) != LS_OK))
+                b = 0;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->held[w] = b;
             }
-            S->peak = S->admitted > S->peak ? S->admitted : S->peak;
-            S->n_batches++;
+            S->cv_work.notify_all();
+            continue;
         }
         ls_status status = ok ? LS_OK : LS_ERR_HIP;
         if (ok) {
@@ -153,6 +234,9 @@ void worker_main(ls_server* S)
                 }
             }
         }
+        size_t kept = 0;
+        if (ok && ls_device_bytes(ctx, &kept) != LS_OK)
+            kept = 0;
         const auto now = Clock::now();
         {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -166,7 +250,12 @@ void worker_main(ls_server* S)
                 S->pending.erase(r.ticket);
                 S->n_completed++;
             }
-            S->admitted -= bytes;
+            S->keys_bytes -= keys * 8;
+            S->large_running -= has_large ? 1u : 0u;
+            // what the context keeps from now on (a bound that was too low
+            // shows here, and the next admissions count it)
+            S->held[w] = kept;
+            S->peak = std::max(S->peak, accounted(S));
         }
         S->cv_done.notify_all();
         S->cv_work.notify_all();
@@ -200,8 +289,14 @@ ls_status ls_server_create(ls_server** out, int device, size_t hbm_budget_bytes,
         S->params = *p;
     else
         ls_default_params(&S->params);
+    size_t probe = 0;
+    if (ls_workspace_size(nullptr, LS_F64, 1, &S->params, &probe) != LS_OK) {
+        delete S;
+        return LS_ERR_INVALID;
+    }
+    S->held.assign(max_inflight, 0);
     for (uint32_t i = 0; i < max_inflight; ++i)
-        S->workers.emplace_back(worker_main, S);
+        S->workers.emplace_back(worker_main, S, i);
     *out = S;
     return LS_OK;
 }
@@ -210,7 +305,7 @@ ls_status ls_server_submit(ls_server* S, ls_dtype dtype, void* d_keys, size_t n,
 {
     if (!S || !ticket || (dtype != LS_F64 && dtype != LS_U64) || (n && !d_keys))
         return LS_ERR_INVALID;
-    if ((uint64_t)n * kBytesPerKey > S->budget)
+    if ((uint64_t)n * 8 + batch_bound(S, n) > S->budget)
         return LS_ERR_BUDGET;
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -253,7 +348,7 @@ ls_status ls_server_stats(ls_server* S, uint64_t* out6)
     out6[1] = S->n_completed;
     out6[2] = S->n_batches;
     out6[3] = S->peak;
-    out6[4] = S->admitted;
+    out6[4] = accounted(S);
     out6[5] = S->queue.size();
     return LS_OK;
 }

@@ -65,29 +65,57 @@ def test_same_result_alone_and_in_the_mix(S):
         assert np.array_equal(words(mixed[i]), expected_sorted(reqs[i]))
 
 
-def test_budget_bounds_admission_and_rejects_oversize():
-    reqs = request_inputs(24, seed=32, hi=1 << 20)
-    biggest = max(a.size for a in reqs)
-    budget = 16 * biggest * 3                    # about three of the largest requests at once
+def batch_bound(S, n):
+    # the server's bound on what a batch of n keys adds to a context
+    return int(S.workspace_size(n) * 1.5) + (8 << 20)
+
+
+def test_budget_bounds_device_memory(S):
+    # The device's free memory is polled while the server runs: what the
+    # server's contexts allocate stays within the budget (whose other part is
+    # the keys in flight, allocated here beforehand), up to what the HIP
+    # runtime takes for the workers' streams.  The budget holds about one
+    # batch of the largest requests at a time, so workers must free the
+    # buffers they keep from earlier batches for the next one to run.
+    reqs = request_inputs(40, seed=32, hi=1 << 22)
     ts = [upload(a) for a in reqs]
     torch.cuda.synchronize()
-    srv = ls.Server(0, hbm_budget=budget, max_inflight=2)
+    biggest = max(a.size for a in reqs)
+    one = biggest * 8 + batch_bound(S, biggest)
+    budget = int(one * 1.3)
+    workers = 3
+    free0 = torch.cuda.mem_get_info(0)[0]
+    srv = ls.Server(0, hbm_budget=budget, max_inflight=workers)
+    peak_used = 0
     try:
-        too_big = torch.empty(budget // 16 + 1, dtype=torch.float64, device="cuda:0")
+        too_big = torch.empty(budget // 8, dtype=torch.float64, device="cuda:0")
         with pytest.raises(ls.LsortError) as e:
             srv.submit(too_big)
         assert e.value.status == 5
+        del too_big
+        torch.cuda.empty_cache()
+        free0 = min(free0, torch.cuda.mem_get_info(0)[0])
         tickets = [srv.submit(t) for t in ts]
         for tk in tickets:
-            srv.wait(tk)
+            while True:
+                try:
+                    srv.wait(tk, timeout_ms=1)
+                    break
+                except ls.LsortError as e:
+                    if e.status != 6:
+                        raise
+                peak_used = max(peak_used, free0 - torch.cuda.mem_get_info(0)[0])
         st = srv.stats()
         with pytest.raises(ls.LsortError) as e:
             srv.wait(10 ** 9)
         assert e.value.status == 7
     finally:
         srv.close()
+    print("budget %.1f MB, peak accounted %.1f MB, peak device use of the server %.1f MB, batches %d" %
+          (budget / 1e6, st["peak_bytes"] / 1e6, peak_used / 1e6, st["batches"]))
+    assert st["completed"] == len(reqs) and st["queued"] == 0
     assert 0 < st["peak_bytes"] <= budget
-    assert st["admitted_bytes"] == 0 and st["queued"] == 0
+    assert peak_used <= budget + workers * (16 << 20), peak_used
     for a, t in zip(reqs, ts):
         assert np.array_equal(words(t), expected_sorted(a))
 
