@@ -439,6 +439,61 @@ def bench_sweep(args, torch, ls):
     S.close()
 
 
+# The spill-bucket ablation (LearnedSort 1.0, Sec. 3 / Fig. 2): Std Normal
+# (no duplicates) and Zipf skews up to 0.99 at 10^8 keys.
+LS1_POINTS = [("normal", 10 ** 8)] + [("zipf%.2f" % s, 10 ** 8) for s in (0.5, 0.7, 0.9, 0.99)]
+
+
+def bench_ls1(args, torch, ls):
+    """One JSON row per LS1_POINTS entry: keys/s of LearnedSort 2.0 (sort_)
+    against the spill-bucket design of LearnedSort 1.0 (sort_ls1_, slack
+    0.1) on the same keys, with the spilled share and LS1's phases; both
+    results checked bit for bit against a library sort on the device."""
+    import workloads as W
+    S = ls.Sorter(0)
+    stream = torch.cuda.current_stream()
+    points = LS1_POINTS
+    if args.sweep_max_n:
+        points = [(f, n) for f, n in points if n <= args.sweep_max_n]
+    for fam, n in points:
+        keys = W.paper_family_large(fam, n, seed=7)
+        pristine = to_device(keys, torch)
+        del keys
+        work = torch.empty_like(pristine)
+        want = library_sorted_words(pristine.view(torch.int64), torch)
+        row = {"metric": METRIC, "workload": "ls1_ablation", "family": fam, "n": n, "unit": "keys/s",
+               "dtype": "f64", "duplicate_ratio": int((want[1:] == want[:-1]).sum()) / n, "slack": 0.1}
+        for mode in ("ls2", "ls1"):
+            ms, st = [], None
+            for step in range(args.warmup + args.steps):
+                work.copy_(pristine)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                if mode == "ls2":
+                    S.sort_(work)
+                else:
+                    st = S.sort_ls1_(work, slack=0.1)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if step >= args.warmup:
+                    ms.append(e0.elapsed_time(e1))
+            exact = bool(torch.equal(work.view(torch.int64), want))
+            m = sum(ms) / len(ms)
+            row[mode] = {"value": n / (m / 1e3), "ms_per_sort": m, "exact_vs_library_sort": exact}
+            if st:
+                row[mode].update({"spilled_frac": st["spilled"] / n, "capacity": st["capacity"],
+                                  "ms_phases_last_sort": {k: st[k] for k in ("ms_partition", "ms_bucket_sorts",
+                                                                             "ms_spill_sort", "ms_merge")}})
+            if not exact:
+                raise SystemExit("ls1 ablation %s n=%d: %s differs from the library sort" % (fam, n, mode))
+        row["value"] = row["ls2"]["value"]
+        row["ls1_over_ls2"] = row["ls1"]["value"] / row["ls2"]["value"]
+        print(json.dumps(row), flush=True)
+        del pristine, work, want
+        torch.cuda.empty_cache()
+    S.close()
+
+
 KERNEL_CLASS_OF = (("k_upload", "upload"), ("k_train", "train"), ("k_hist", "hist"), ("k_scan", "scan"),
                    ("k_classify", "classify"),
                    ("k_layout", "classify"), ("k_round_init", "classify"), ("k_scatter", "scatter"),
@@ -585,6 +640,8 @@ def main():
         return bench_served(args, torch, ls)
     if args.workload == "sweep":
         return bench_sweep(args, torch, ls)
+    if args.workload == "ls1":
+        return bench_ls1(args, torch, ls)
 
     t_gen = time.perf_counter()
     keys, wname, n = make_workload(args.workload, args.n)

@@ -187,6 +187,23 @@ typedef struct {
     double   ms;               /* fastest repetition; < 0: does not fit this device, not run */
 } ls_tune_result;
 
+/* LearnedSort 1.0's spill bucket, as an ablation against the fragment
+ * partition (Sec. 2, Fig. 1, Sec. 3).  Sorts d_keys (device, n keys of
+ * dtype, in place; the same result as ls_sort_f64/u64) the way LS1 did:
+ * one partition by the global model into p->fanout buckets of fixed
+ * capacity ceil(n (1 + slack) / fanout); the keys a full bucket cannot take
+ * go to a spill bucket.  The buckets are sorted (this library's pipeline,
+ * as segments), the spill bucket by a general-purpose sort (rocPRIM's radix
+ * sort, standing in for LS1's std::sort), and the two are merged (rocPRIM).
+ * With many repeated keys the spill bucket grows, and so does the work of
+ * the last two steps.  out8 (host, may be NULL): [0] spilled keys, [1] the
+ * capacity, [2] ms partition (model, counts, scatter), [3] ms bucket sorts,
+ * [4] ms spill sort, [5] ms pack, merge and conversion, [6] ms in all,
+ * [7] fanout.  Synchronous.  Device memory: about (2 + slack) n x 8 B plus
+ * 2 x 8 B per spilled key, besides the sort's own scratch. */
+ls_status ls_sort_ls1(ls_ctx* ctx, ls_dtype dtype, void* d_keys, size_t n, double slack, ls_stream_t stream,
+                      const ls_params* p, double* out8);
+
 /* Autotuner for the GPU-specific knobs (fanout, LDS tile, base-case
  * threshold; the paper fixes f = 1000, c = 100 for its CPU, Sec. 6.1).
  * Sorts a library-owned copy of the `count` arrays (HOST list, device keys;

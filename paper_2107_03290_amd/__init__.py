@@ -48,7 +48,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime er
 # C-ABI entry points declared in include/lsort.h
 EXPORTS = (
     "ls_create", "ls_destroy", "ls_default_params", "ls_workspace_size", "ls_reserve", "ls_device_bytes", "ls_trim",
-    "ls_sort_f64", "ls_sort_u64", "ls_sort_noalloc", "ls_sort_segments", "ls_sort_arrays", "ls_autotune", "ls_sync",
+    "ls_sort_f64", "ls_sort_u64", "ls_sort_noalloc", "ls_sort_segments", "ls_sort_arrays", "ls_sort_ls1",
+    "ls_autotune", "ls_sync",
     "ls_last_stats", "ls_last_profile", "ls_profile_reset", "ls_status_string", "ls_last_error",
     "ls_model_train", "ls_stage_hist",
     "ls_server_create", "ls_server_submit", "ls_server_wait", "ls_server_stats",
@@ -114,6 +115,8 @@ def lib() -> ctypes.CDLL:
             L.ls_sort_noalloc.argtypes = [vp, ctypes.c_int, vp, sz, vp, P(Params)]
             L.ls_sort_segments.argtypes = [vp, ctypes.c_int, vp, P(u64), sz, P(ctypes.c_uint8), vp, P(Params)]
             L.ls_sort_arrays.argtypes = [vp, P(Array), sz, vp, P(Params)]
+            L.ls_sort_ls1.argtypes = [vp, ctypes.c_int, vp, sz, ctypes.c_double, vp, P(Params),
+                                      P(ctypes.c_double)]
             L.ls_autotune.argtypes = [vp, P(Array), sz, vp, P(Params), ctypes.c_uint32, P(Params),
                                       P(TuneResult), sz, P(sz)]
             L.ls_sync.argtypes = [vp, P(ctypes.c_uint32)]
@@ -284,6 +287,18 @@ class Sorter:
 
     def profile_reset(self):
         self._check(lib().ls_profile_reset(self._ctx))
+
+    def sort_ls1_(self, t, slack: float = 0.1, p: Params | None = None) -> dict:
+        """LearnedSort 1.0's spill-bucket sort of t in place (the ablation of
+        ls_sort_ls1; the same result as sort_).  Returns its counters and
+        per-phase milliseconds."""
+        _check_tensor(t)
+        out = (ctypes.c_double * 8)()
+        self._check(lib().ls_sort_ls1(self._ctx, _dtype_code(t), t.data_ptr(), t.numel(), slack,
+                                      _stream_handle(t), _pp(p), out))
+        keys = ("spilled", "capacity", "ms_partition", "ms_bucket_sorts", "ms_spill_sort", "ms_merge", "ms_total",
+                "fanout")
+        return dict(zip(keys, [float(x) for x in out]))
 
     def device_bytes(self) -> int:
         """Device memory the context's work buffers hold now."""

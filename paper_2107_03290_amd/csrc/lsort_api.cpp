@@ -1672,6 +1672,145 @@ ls_status ls_sort_segments(ls_ctx* C, ls_dtype dtype, void* d_keys, const uint64
     return sort_arrays(C, a, (hipStream_t)stream, p);
 }
 
+ls_status ls_sort_ls1(ls_ctx* C, ls_dtype dtype, void* d_keys, size_t n, double slack, ls_stream_t stream,
+                      const ls_params* p, double* out8)
+{
+    GateUse gate;
+    if (!C)
+        return LS_ERR_INVALID;
+    if ((dtype != LS_F64 && dtype != LS_U64) || (n && !d_keys) || !(slack >= 0.0) || slack > 64.0)
+        return fail(C, LS_ERR_INVALID, "ls_sort_ls1: dtype, keys or slack (0..64) invalid");
+    if (((uintptr_t)d_keys) & 7u)
+        return fail(C, LS_ERR_INVALID, "key buffer must be 8-byte aligned");
+    Params P;
+    TRY(resolve(C, p, P));
+    P.flags &= ~(uint32_t)(LS_FLAG_GRAPH | LS_FLAG_INPLACE | LS_FLAG_PROFILE);
+    HIPCHECK(C, hipSetDevice(C->device));
+    C->dev_status = 0;
+    std::memset(C->stats, 0, sizeof C->stats);
+    if (out8)
+        std::fill(out8, out8 + 8, 0.0);
+    if (n <= 1)
+        return LS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t f = P.fanout, L = P.leaves;
+    if (ls1_scatter_lds_bytes(f, L) > C->lds_limit)
+        return fail(C, LS_ERR_UNSUPPORTED, "ls_sort_ls1: fanout and leaves exceed the LDS of one workgroup");
+    const uint64_t cap = std::max<uint64_t>(1, (uint64_t)std::ceil((double)n * (1.0 + slack) / (double)f));
+    hipEvent_t ev[5] = {};
+    for (auto& e : ev)
+        HIPCHECK(C, hipEventCreate(&e));
+    struct EvFree {
+        hipEvent_t* e;
+        ~EvFree()
+        {
+            for (int i = 0; i < 5; ++i)
+                if (e[i])
+                    (void)hipEventDestroy(e[i]);
+        }
+    } evfree{ev};
+    HIPCHECK(C, hipEventRecord(ev[0], st));
+    // 1. the global model (Sec. 2), 2. bucket counts per chunk and their scan
+    Trainer tr;
+    tr.add((const uint64_t*)d_keys, n, sample_size(n, P.rate, P.cap), P.seed, L, dtype);
+    TRY(ensure(C, C->gjobs, sizeof(ModelJob), st));
+    TRY(upload(C, C->pin_jobs, C->gjobs, tr.jobs, st));
+    TRY(train(C, C->gjobs, 1, tr.blocks, tr.samples, tr.leaves, tr.max_sample, 0, tr.models, st, nullptr));
+    const uint64_t chunk = std::max<uint64_t>(
+        kLs1Tile * 4ull, ((n + kTargetChunks - 1) / kTargetChunks + kLs1Tile - 1) / kLs1Tile * kLs1Tile);
+    Task t{};
+    t.keys = (uint64_t*)d_keys;
+    t.n = n;
+    t.scale = (double)f;
+    t.fanout = f;
+    t.kind = kGlobal;
+    t.dtype = dtype;
+    t.leaves = L;
+    t.nchunks = (uint32_t)((n + chunk - 1) / chunk);
+    const uint64_t entries = (uint64_t)f * t.nchunks;
+    TRY(ensure(C, C->tasks, sizeof(Task), st));
+    TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
+    TRY(ensure(C, C->cnt, entries * 4, st));
+    TRY(ensure(C, C->pos, entries * 8, st));
+    TRY(ensure(C, C->pcnt, entries * 4, st));
+    TRY(ensure(C, C->ppos, entries * 8, st));
+    TRY(ensure(C, C->scantmp, scan_tmp_entries(entries) * 8, st));
+    TRY(ensure(C, C->bstat, (size_t)f * 16, st));
+    TRY(ensure(C, C->fullb, ((size_t)f + 2) * 8, st));
+    HIPCHECK(C, hipMemcpyAsync(C->tasks.p, &t, sizeof(Task), hipMemcpyHostToDevice, st));
+    HIPCHECK(C, launch_round_init((uint64_t*)C->bstat.p, f, (RoundCtl*)C->ctl.p, false, st));
+    HIPCHECK(C, launch_hist((const Task*)C->tasks.p, 1, t.nchunks, chunk, (const double*)C->models.p,
+                            (uint32_t*)C->cnt.p, (uint64_t*)C->bstat.p, f, L, 0, nullptr, st));
+    HIPCHECK(C, launch_scan((const uint32_t*)C->cnt.p, (uint64_t*)C->pos.p, entries, (uint64_t*)C->scantmp.p,
+                            nullptr, st));
+    // 3. what spills from each (bucket, chunk) entry, and where it goes
+    HIPCHECK(C, launch_ls1_spill_counts((const uint64_t*)C->pos.p, (const uint32_t*)C->cnt.p, entries, t.nchunks,
+                                        cap, (uint32_t*)C->pcnt.p, st));
+    HIPCHECK(C, launch_scan((const uint32_t*)C->pcnt.p, (uint64_t*)C->ppos.p, entries, (uint64_t*)C->scantmp.p,
+                            nullptr, st));
+    HIPCHECK(C, launch_ls1_buckets((const uint64_t*)C->pos.p, (const uint64_t*)C->ppos.p,
+                                   (const uint32_t*)C->pcnt.p, f, t.nchunks, n, (uint64_t*)C->fullb.p, st));
+    std::vector<uint64_t> bt((size_t)f + 2);
+    HIPCHECK(C, hipMemcpyAsync(bt.data(), C->fullb.p, bt.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(C, hipStreamSynchronize(st));
+    const uint64_t nspill = bt[f + 1], nkept = n - nspill;
+    // 4. the ablation's own area: bucket slots, spill, sorted spill, packed
+    // buckets, merged run, library temp
+    size_t tb_sort = 0, tb_merge = 0;
+    HIPCHECK(C, ls1_radix_sort(nullptr, &tb_sort, nullptr, nullptr, nspill, st));
+    HIPCHECK(C, ls1_merge(nullptr, &tb_merge, nullptr, nkept, nullptr, nspill, nullptr, st));
+    const uint64_t slots_n = (uint64_t)f * cap;
+    const size_t temp = (std::max(tb_sort, tb_merge) + 255) & ~(size_t)255;
+    TRY(ensure(C, C->tune, (slots_n + 2 * nspill + nkept + n) * 8 + temp, st));
+    uint64_t* slots = (uint64_t*)C->tune.p;
+    uint64_t* spill = slots + slots_n;
+    uint64_t* sorted = spill + nspill;
+    uint64_t* packed = sorted + nspill;
+    uint64_t* merged = packed + nkept;
+    void* tmp = merged + n;
+    HIPCHECK(C, launch_scatter_ls1((const Task*)C->tasks.p, t.nchunks, chunk, (const double*)C->models.p,
+                                   (const uint64_t*)C->pos.p, (const uint64_t*)C->ppos.p, cap, slots, spill, f, L,
+                                   st));
+    HIPCHECK(C, hipEventRecord(ev[1], st));
+    // 5. each bucket sorted (the library's pipeline, buckets as segments)
+    std::vector<Array> arrays;
+    std::vector<uint64_t> fill((size_t)f + 1, 0);
+    arrays.reserve(f);
+    for (uint32_t b = 0; b < f; ++b) {
+        const uint64_t m = std::min<uint64_t>(bt[b + 1] - bt[b], cap);
+        fill[b + 1] = fill[b] + m;
+        arrays.push_back(Array{slots + (uint64_t)b * cap, nullptr, m, (uint32_t)dtype});
+    }
+    TRY(run_pipeline(C, arrays, st, P, false));
+    HIPCHECK(C, hipEventRecord(ev[2], st));
+    // 6. the spill area sorted
+    if (nspill)
+        HIPCHECK(C, ls1_radix_sort(tmp, &tb_sort, spill, sorted, nspill, st));
+    HIPCHECK(C, hipEventRecord(ev[3], st));
+    // 7. buckets packed, merged with the spill area, converted back
+    TRY(ensure(C, C->fullb, ((size_t)f + 2) * 8, st));
+    HIPCHECK(C, hipMemcpyAsync(C->fullb.p, fill.data(), fill.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHECK(C, launch_ls1_compact(slots, (const uint64_t*)C->fullb.p, cap, f, dtype, packed, st));
+    HIPCHECK(C, ls1_merge(tmp, &tb_merge, packed, nkept, sorted, nspill, merged, st));
+    HIPCHECK(C, launch_from_ord(merged, n, dtype, (uint64_t*)d_keys, st));
+    HIPCHECK(C, hipEventRecord(ev[4], st));
+    HIPCHECK(C, hipEventSynchronize(ev[4]));
+    if (out8) {
+        out8[0] = (double)nspill;
+        out8[1] = (double)cap;
+        for (int i = 0; i < 4; ++i) {
+            float ms = 0.f;
+            HIPCHECK(C, hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            out8[2 + i] = ms;
+        }
+        float all = 0.f;
+        HIPCHECK(C, hipEventElapsedTime(&all, ev[0], ev[4]));
+        out8[6] = all;
+        out8[7] = (double)f;
+    }
+    return LS_OK;
+}
+
 ls_status ls_sort_arrays(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_stream_t stream,
                          const ls_params* p)
 {

@@ -233,6 +233,13 @@ __host__ __device__ inline size_t model_lds_bytes(uint32_t L)
     return (size_t)(L + 1) * 40 + (size_t)L * 2 + 32;
 }
 
+// Spill-bucket partition (LearnedSort 1.0 ablation): its scatter tile, and
+// its LDS (the scatter's, the model rounded up to 16 bytes, three words per
+// bucket).
+constexpr uint32_t kLs1Tile = 4096;
+__host__ __device__ inline size_t ls1_model_lds_bytes(uint32_t L) { return (model_lds_bytes(L) + 15) & ~(size_t)15; }
+size_t ls1_scatter_lds_bytes(uint32_t fanout, uint32_t leaves);
+
 // Keys of a round from which the default tile is doubled: a larger tile
 // makes longer runs per bucket in the scatter's writes, and a round this
 // large still has thousands of chunks.
@@ -325,6 +332,25 @@ hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t*
 // to host_ctl.
 hipError_t launch_layout(Task* d_next, ModelJob* d_jobs, const LayoutParams& lp, RoundCtl* d_ctl,
                          RoundCtl* host_ctl, hipStream_t st);
+// Spill-bucket ablation (LearnedSort 1.0): the fixed-capacity partition of
+// one task (d_task, a global-model task over the whole array), its spill
+// counts per (bucket, chunk) entry, the bucket table, the packing of the
+// sorted buckets into order words, the conversion back, and the library sort
+// and merge of the spill area (a null temp asks for the temp size).
+hipError_t launch_scatter_ls1(const Task* d_task, uint32_t nchunks, uint64_t chunk, const double* d_models,
+                              const uint64_t* d_pos, const uint64_t* d_spoff, uint64_t cap, uint64_t* d_dst,
+                              uint64_t* d_spill, uint32_t fanout, uint32_t leaves, hipStream_t st);
+hipError_t launch_ls1_spill_counts(const uint64_t* d_pos, const uint32_t* d_cnt, uint64_t entries,
+                                   uint32_t nchunks, uint64_t cap, uint32_t* d_spilled, hipStream_t st);
+hipError_t launch_ls1_buckets(const uint64_t* d_pos, const uint64_t* d_spoff, const uint32_t* d_spilled,
+                              uint32_t fanout, uint32_t nchunks, uint64_t n, uint64_t* d_out, hipStream_t st);
+hipError_t launch_ls1_compact(const uint64_t* d_slots, const uint64_t* d_fill, uint64_t cap, uint32_t fanout,
+                              uint32_t dtype, uint64_t* d_out, hipStream_t st);
+hipError_t launch_from_ord(const uint64_t* d_ord, uint64_t n, uint32_t dtype, uint64_t* d_out, hipStream_t st);
+hipError_t ls1_radix_sort(void* d_temp, size_t* temp_bytes, const uint64_t* d_in, uint64_t* d_out, uint64_t n,
+                          hipStream_t st);
+hipError_t ls1_merge(void* d_temp, size_t* temp_bytes, const uint64_t* d_a, uint64_t na, const uint64_t* d_b,
+                     uint64_t nb, uint64_t* d_out, hipStream_t st);
 // The scatter evaluates each key's bucket again from the task's model (the
 // same arithmetic as the histogram).
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,

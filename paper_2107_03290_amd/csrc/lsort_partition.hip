@@ -785,6 +785,10 @@ struct ScatterLds {
     uint32_t* tstart;
     uint16_t* sb;
     void* model;
+    // spill-bucket rounds (k_scatter_ls1): per bucket {slot offset, first
+    // position past its capacity, spill offset}, all relative to a key's
+    // position in the task's count-ordered layout
+    uint64_t* ls1;
 };
 
 __device__ __forceinline__ ScatterLds scatter_lds(unsigned char* smem, uint32_t tile, uint32_t f)
@@ -806,10 +810,10 @@ __device__ __forceinline__ ScatterLds scatter_lds(unsigned char* smem, uint32_t 
 // write loop needs none behind it: the next tile's ranking touches only the
 // counts and the cursors' skip bits, and everything the write loop reads is
 // rewritten only after the next tile's first barrier.
-template <uint32_t KPT, uint32_t DT, bool MSD>
+template <uint32_t KPT, uint32_t DT, bool MSD, bool LS1 = false>
 __device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, gptr<const uint64_t> src,
                                              gptr<uint64_t> dst, uint32_t n, const ScatterLds& L,
-                                             uint32_t* wsum, uint32_t flags)
+                                             uint32_t* wsum, uint32_t flags, gptr<uint64_t> spill = {})
 {
     constexpr uint32_t NT = kScatterThreads;
     constexpr uint32_t TILE = KPT * NT;
@@ -893,8 +897,21 @@ __device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, gpt
             }
         }
         __syncthreads();
-        for (uint32_t p = threadIdx.x; p < ntile; p += NT)
-            dst[L.wbase[L.sb[p]] + p] = L.stage[p];
+        if (!LS1) {
+            for (uint32_t p = threadIdx.x; p < ntile; p += NT)
+                dst[L.wbase[L.sb[p]] + p] = L.stage[p];
+        } else {
+            // a key whose rank in its bucket is below the capacity takes its
+            // slot in the bucket; the rest go to the spill area as order words
+            for (uint32_t p = threadIdx.x; p < ntile; p += NT) {
+                const uint32_t b = L.sb[p];
+                const uint64_t g = L.wbase[b] + p;
+                if (g < L.ls1[3 * b + 1])
+                    dst[g + L.ls1[3 * b]] = L.stage[p];
+                else
+                    spill[g + L.ls1[3 * b + 2]] = to_ord(L.stage[p], DT);
+            }
+        }
     }
 }
 
@@ -945,6 +962,62 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, 
         if (msd) scatter_body<KPT, kU64, true>(T, M, src, dst, n, L, wsum, flags);
         else scatter_body<KPT, kU64, false>(T, M, src, dst, n, L, wsum, flags);
     }
+}
+
+// Partition of LearnedSort 1.0 (Sec. 2, Fig. 1) for the spill-bucket
+// ablation: one task, every bucket b holds at most `cap` keys in the slots
+// [b cap, (b + 1) cap) of dst; the keys of a bucket past its capacity go to
+// the spill area (order words), entry (b, chunk) of them at spoff[entry].
+// Ranks inside a bucket follow the count-ordered layout of pos (chunk by
+// chunk), so which keys spill is fixed by the scan; their order in the spill
+// area does not matter (it is sorted).
+template <uint32_t KPT>
+__global__ __launch_bounds__(kScatterThreads) void k_scatter_ls1(const Task* tasks, uint64_t chunk,
+                                                                 const double* models, const uint64_t* pos,
+                                                                 const uint64_t* spoff, uint64_t cap,
+                                                                 uint64_t* dst, uint64_t* spill, uint32_t flags)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr uint32_t TILE = KPT * kScatterThreads;
+    __shared__ uint32_t wsum[kScatterThreads / 64 + 1];
+    const Task T = tasks[0];
+    const uint32_t f = T.fanout;
+    ScatterLds L = scatter_lds(smem, TILE, f);
+    L.ls1 = reinterpret_cast<uint64_t*>(reinterpret_cast<unsigned char*>(L.model) +
+                                        ls1_model_lds_bytes(T.leaves));
+    const uint32_t lc = blockIdx.x;
+    for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
+        const uint64_t e = (uint64_t)b * T.nchunks;
+        const uint64_t start = pos[e], c = pos[e + lc];
+        const uint64_t lim = start + cap;
+        L.cur[b] = c;
+        L.tcnt[b] = 0;
+        L.ls1[3 * b] = (uint64_t)b * cap - start;                 // modulo 2^64
+        L.ls1[3 * b + 1] = lim;
+        L.ls1[3 * b + 2] = spoff[e + lc] - (c > lim ? c : lim);   // modulo 2^64
+    }
+    SModel M{};
+    load_model(M, models, T.model, T.leaves, L.model);
+    __syncthreads();
+    const uint64_t lo = (uint64_t)lc * chunk;
+    const uint32_t n = (uint32_t)(min(T.n, lo + chunk) - lo);
+    const gptr<const uint64_t> src = as_global<const uint64_t>(T.keys + lo);
+    if (T.dtype == kF64)
+        scatter_body<KPT, kF64, false, true>(T, M, src, as_global(dst), n, L, wsum, flags, as_global(spill));
+    else
+        scatter_body<KPT, kU64, false, true>(T, M, src, as_global(dst), n, L, wsum, flags, as_global(spill));
+}
+
+hipError_t launch_scatter_ls1(const Task* d_task, uint32_t nchunks, uint64_t chunk, const double* d_models,
+                              const uint64_t* d_pos, const uint64_t* d_spoff, uint64_t cap, uint64_t* d_dst,
+                              uint64_t* d_spill, uint32_t fanout, uint32_t leaves, hipStream_t st)
+{
+    if (!nchunks)
+        return hipSuccess;
+    const size_t smem = ls1_scatter_lds_bytes(fanout, leaves);
+    k_scatter_ls1<kLs1Tile / kScatterThreads><<<nchunks, kScatterThreads, smem, st>>>(
+        d_task, chunk, d_models, d_pos, d_spoff, cap, d_dst, d_spill, 0u);
+    return hipGetLastError();
 }
 
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
