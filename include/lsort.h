@@ -165,6 +165,21 @@ ls_status ls_sort_segments(ls_ctx* ctx, ls_dtype dtype, void* d_keys, const uint
                            size_t num_segments, const uint8_t* h_dtypes, ls_stream_t stream,
                            const ls_params* p);
 
+/* ls_sort_segments with the batch described on the DEVICE: d_offsets
+ * (num_segments + 1 entries, d_offsets[0] = 0, non-decreasing) and d_dtypes
+ * (num_segments ls_dtype bytes, or NULL for `dtype`) in device memory, so a
+ * batch already resident on the device needs no host copy of its
+ * description.  A kernel prepares round 0 from them (groups of small
+ * segments, one global-model task per large segment); the host reads back
+ * only the total key count (to size the scratch) and round 0's counts.
+ * Invalid offsets are found on the device and reported as LS_ERR_INVALID.
+ * The same result as ls_sort_segments.  LS_FLAG_GRAPH is ignored
+ * (host-driven rounds).  Returns once round 0's counts are read; the sort
+ * completes on `stream`. */
+ls_status ls_sort_segments_device(ls_ctx* ctx, ls_dtype dtype, void* d_keys, const uint64_t* d_offsets,
+                                  size_t num_segments, const uint8_t* d_dtypes, ls_stream_t stream,
+                                  const ls_params* p);
+
 /* One array of a batch: its own device buffer, length and key type. */
 typedef struct {
     void*    d_keys;

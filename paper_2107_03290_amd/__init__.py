@@ -48,7 +48,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime er
 # C-ABI entry points declared in include/lsort.h
 EXPORTS = (
     "ls_create", "ls_destroy", "ls_default_params", "ls_workspace_size", "ls_reserve", "ls_device_bytes", "ls_trim",
-    "ls_sort_f64", "ls_sort_u64", "ls_sort_noalloc", "ls_sort_segments", "ls_sort_arrays", "ls_sort_ls1",
+    "ls_sort_f64", "ls_sort_u64", "ls_sort_noalloc", "ls_sort_segments", "ls_sort_segments_device",
+    "ls_sort_arrays", "ls_sort_ls1",
     "ls_autotune", "ls_sync",
     "ls_last_stats", "ls_last_profile", "ls_profile_reset", "ls_status_string", "ls_last_error",
     "ls_model_train", "ls_stage_hist",
@@ -115,6 +116,7 @@ def lib() -> ctypes.CDLL:
             L.ls_sort_noalloc.argtypes = [vp, ctypes.c_int, vp, sz, vp, P(Params)]
             L.ls_sort_segments.argtypes = [vp, ctypes.c_int, vp, P(u64), sz, P(ctypes.c_uint8), vp, P(Params)]
             L.ls_sort_arrays.argtypes = [vp, P(Array), sz, vp, P(Params)]
+            L.ls_sort_segments_device.argtypes = [vp, ctypes.c_int, vp, vp, sz, vp, vp, P(Params)]
             L.ls_sort_ls1.argtypes = [vp, ctypes.c_int, vp, sz, ctypes.c_double, vp, P(Params),
                                       P(ctypes.c_double)]
             L.ls_autotune.argtypes = [vp, P(Array), sz, vp, P(Params), ctypes.c_uint32, P(Params),
@@ -225,6 +227,22 @@ class Sorter:
         off = (ctypes.c_uint64 * (n + 1))(*[int(x) for x in offsets])
         dt = (ctypes.c_uint8 * n)(*[int(x) for x in dtypes]) if dtypes is not None else None
         self._check(lib().ls_sort_segments(self._ctx, code, t.data_ptr(), off, n, dt, _stream_handle(t), _pp(p)))
+        return t
+
+    def sort_segments_device_(self, t, d_offsets, d_dtypes=None, p: Params | None = None):
+        """sort_segments_ with the batch described by device tensors:
+        d_offsets (int64, num_segments + 1 entries) and d_dtypes (uint8
+        ls_dtype codes, or None for t's type), both on t's device."""
+        _check_tensor(t)
+        if not d_offsets.is_cuda or d_offsets.dtype.itemsize != 8 or not d_offsets.is_contiguous():
+            raise ValueError("d_offsets must be a contiguous 64-bit device tensor")
+        if d_dtypes is not None and (not d_dtypes.is_cuda or d_dtypes.element_size() != 1 or
+                                     not d_dtypes.is_contiguous()):
+            raise ValueError("d_dtypes must be a contiguous 8-bit device tensor")
+        n = d_offsets.numel() - 1
+        dt = d_dtypes.data_ptr() if d_dtypes is not None else None
+        self._check(lib().ls_sort_segments_device(self._ctx, _dtype_code(t), t.data_ptr(), d_offsets.data_ptr(),
+                                                  max(n, 0), dt, _stream_handle(t), _pp(p)))
         return t
 
     def sort_arrays_(self, tensors: Sequence, p: Params | None = None):

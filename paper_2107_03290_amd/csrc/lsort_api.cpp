@@ -59,14 +59,6 @@ struct Array {
     uint32_t dtype;
 };
 
-uint64_t sample_size(uint64_t n, double rate, uint64_t cap)
-{
-    double want = std::ceil(rate * (double)n);
-    uint64_t m = want < 1.0 ? 1u : (uint64_t)want;
-    if (cap && m > cap)
-        m = cap;
-    return m;
-}
 
 // A captured replay of one batch size class (keys, arrays), valid while no
 // buffer it uses has been reallocated (gen).
@@ -86,10 +78,6 @@ struct RoundsHint {
     uint32_t rounds;
 };
 
-uint32_t group_class(uint32_t n)
-{
-    return n <= kGroupClassCap[0] ? 0u : (n <= kGroupClassCap[1] ? 1u : 2u);
-}
 
 }  // namespace
 
@@ -1380,6 +1368,89 @@ ls_status run_pipeline_marked(ls_ctx* C, std::vector<Array>& arrays, hipStream_t
     return s;
 }
 
+// A batch of segments described on the device: round 0 is prepared by a
+// kernel from the device offsets (no host walk of the segments); the rest is
+// the host-driven pipeline.  Two small reads: the total (to size the
+// scratch) and round 0's counts.
+ls_status run_segments_device(ls_ctx* C, uint64_t* keys, const uint64_t* d_off, uint64_t nseg,
+                              const uint8_t* d_dtypes, uint32_t dtype, hipStream_t st, const Params& P)
+{
+    const bool inplace = (P.flags & LS_FLAG_INPLACE) != 0;
+    uint64_t total = 0;
+    if (nseg) {
+        HIPCHECK(C, hipMemcpyAsync(&total, d_off + nseg, 8, hipMemcpyDeviceToHost, st));
+        HIPCHECK(C, hipStreamSynchronize(st));
+    }
+    if (total && !keys)
+        return fail(C, LS_ERR_INVALID, "null key pointer with keys to sort");
+    if (!inplace)
+        TRY(ensure(C, C->scratch, std::max<uint64_t>(total, 1) * 8, st));
+    const size_t slots = std::max<uint64_t>(nseg, 1);
+    TRY(ensure(C, C->ctl, sizeof(RoundCtl), st));
+    TRY(ensure(C, C->next, slots * sizeof(Task), st));
+    TRY(ensure(C, C->ljobs, slots * sizeof(ModelJob), st));
+    TRY(ensure(C, C->gjobs, slots * sizeof(ModelJob), st));
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        TRY(ensure(C, C->groups[c], slots * sizeof(Group), st));
+    TRY(ensure(C, C->skip, kSegSummary * 8, st));
+    SegPrepare A{};
+    A.keys = keys;
+    A.scratch = inplace ? nullptr : (uint64_t*)C->scratch.p;
+    A.off = d_off;
+    A.dtypes = d_dtypes;
+    A.nseg = nseg;
+    A.dtype = dtype;
+    A.base = P.base;
+    A.fanout = P.fanout;
+    A.leaves = P.leaves;
+    A.inplace = inplace ? 1u : 0u;
+    A.rate = P.rate;
+    A.cap = P.cap;
+    A.seed = P.seed;
+    A.tasks = (Task*)C->next.p;
+    A.jobs = (ModelJob*)C->gjobs.p;
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        A.groups[c] = (Group*)C->groups[c].p;
+    A.ctl = (RoundCtl*)C->ctl.p;
+    A.summary = (uint64_t*)C->skip.p;
+    HIPCHECK(C, launch_seg_prepare(A, st));
+    uint64_t sum[kSegSummary] = {};
+    HIPCHECK(C, hipMemcpyAsync(sum, C->skip.p, sizeof sum, hipMemcpyDeviceToHost, st));
+    TRY(read_ctl(C, st));
+    if (sum[3])
+        return fail(C, LS_ERR_INVALID, "offsets must start at 0 and be non-decreasing");
+    const RoundCtl c0 = *C->h_ctl;
+    Prof prof{C, st, (P.flags & LS_FLAG_PROFILE) != 0, {}};
+    prof.only = (int)((P.flags >> 8) & 0xfu) - 1;
+    if (c0.cur.njobs)
+        TRY(train(C, C->gjobs, c0.cur.njobs, c0.cur.blocks, c0.cur.samples, sum[1], c0.cur.max_sample, 0, sum[2],
+                  st, &prof));
+    const LayoutParams lp = layout_params(P, sum[2]);
+    if (c0.ntasks) {
+        LayoutParams lp0 = lp;
+        lp0.host_flag = C->d_h_flag;
+        arm_publish(C);
+        HIPCHECK(C, launch_layout((Task*)C->next.p, (ModelJob*)C->ljobs.p, lp0, (RoundCtl*)C->ctl.p, C->d_h_ctl,
+                                  st));
+        TRY(wait_published(C, st));
+    }
+    TRY(rounds_eager(C, st, P, lp, P.flags & LS_FLAG_NONMONOTONE, prof));
+    TRY(finish_eager(C, st, P, prof, sum[0]));
+    std::vector<Array> arrays;
+    if (C->h_ctl->violations) {
+        // the touch-up repair pass needs the segments on the host
+        std::vector<uint64_t> off(nseg + 1);
+        std::vector<uint8_t> dts(nseg, (uint8_t)dtype);
+        HIPCHECK(C, hipMemcpyAsync(off.data(), d_off, off.size() * 8, hipMemcpyDeviceToHost, st));
+        if (d_dtypes)
+            HIPCHECK(C, hipMemcpyAsync(dts.data(), d_dtypes, nseg, hipMemcpyDeviceToHost, st));
+        HIPCHECK(C, hipStreamSynchronize(st));
+        for (uint64_t i = 0; i < nseg; ++i)
+            arrays.push_back(Array{keys + off[i], nullptr, off[i + 1] - off[i], dts[i]});
+    }
+    return conclude(C, arrays, st, P, false);
+}
+
 ls_status sort_arrays(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const ls_params* p)
 {
     GateUse gate;
@@ -1809,6 +1880,32 @@ ls_status ls_sort_ls1(ls_ctx* C, ls_dtype dtype, void* d_keys, size_t n, double 
         out8[7] = (double)f;
     }
     return LS_OK;
+}
+
+ls_status ls_sort_segments_device(ls_ctx* C, ls_dtype dtype, void* d_keys, const uint64_t* d_offsets,
+                                  size_t num_segments, const uint8_t* d_dtypes, ls_stream_t stream,
+                                  const ls_params* p)
+{
+    GateUse gate;
+    if (!C)
+        return LS_ERR_INVALID;
+    if (num_segments && !d_offsets)
+        return fail(C, LS_ERR_INVALID, "null offsets");
+    if (!d_dtypes && dtype != LS_F64 && dtype != LS_U64)
+        return fail(C, LS_ERR_INVALID, "unknown dtype");
+    if (((uintptr_t)d_keys) & 7u)
+        return fail(C, LS_ERR_INVALID, "key buffer must be 8-byte aligned");
+    Params P;
+    TRY(resolve(C, p, P));
+    P.flags &= ~(uint32_t)LS_FLAG_GRAPH;      // host-driven rounds only
+    HIPCHECK(C, hipSetDevice(C->device));
+    C->dev_status = 0;
+    std::memset(C->stats, 0, sizeof C->stats);
+    hipStream_t st = (hipStream_t)stream;
+    const ls_status s = run_segments_device(C, (uint64_t*)d_keys, d_offsets, num_segments, d_dtypes,
+                                            (uint32_t)dtype, st, P);
+    mark_done(C, st);
+    return s;
 }
 
 ls_status ls_sort_arrays(ls_ctx* C, const ls_array* h_arrays, size_t count, ls_stream_t stream,

@@ -280,6 +280,49 @@ __host__ __device__ inline uint32_t child_fanout(uint64_t n, uint32_t thresh, ui
     return f > cap ? cap : f;
 }
 
+// Sample size of a global model over n keys (rate, at least 1, at most cap
+// when cap is nonzero).
+__host__ __device__ inline uint64_t sample_size(uint64_t n, double rate, uint64_t cap)
+{
+    const double want = ceil(rate * (double)n);
+    uint64_t m = want < 1.0 ? 1u : (uint64_t)want;
+    if (cap && m > cap)
+        m = cap;
+    return m;
+}
+
+// Base-case size class of a group of n keys.
+__host__ __device__ inline uint32_t group_class(uint32_t n)
+{
+    return n <= kGroupClassCap[0] ? 0u : (n <= kGroupClassCap[1] ? 1u : 2u);
+}
+
+// Round 0 of a batch of segments described on the device (offsets and dtypes
+// in device memory): the kernel writes what the host-side preparation writes
+// for host-described arrays (groups of small segments, one global-model task
+// and its training job per large segment, the round-0 control block) and a
+// summary for the host.
+struct SegPrepare {
+    uint64_t* keys;
+    uint64_t* scratch;            // null in place
+    const uint64_t* off;          // nseg + 1 offsets
+    const uint8_t* dtypes;        // null: every segment has `dtype`
+    uint64_t nseg;
+    uint32_t dtype, base, fanout, leaves, inplace, pad;
+    double rate;
+    uint64_t cap, seed;
+    Task* tasks;
+    ModelJob* jobs;
+    Group* groups[kGroupClasses];
+    RoundCtl* ctl;
+    uint64_t* summary;            // kSegSummary words
+};
+// summary: [0] keys in base-case groups, [1] leaf-table entries of sampled
+// jobs, [2] model-pool doubles, [3] nonzero when the offsets are invalid
+// (offsets[0] != 0 or decreasing)
+constexpr uint32_t kSegSummary = 4;
+hipError_t launch_seg_prepare(const SegPrepare& A, hipStream_t st);
+
 // Round-0 lists staged in pinned, device-mapped host memory: the control
 // block at offset 0, then the tasks, the global training jobs and the groups
 // of each size class at the given offsets.  The counts are the staged control

@@ -1020,6 +1020,157 @@ hipError_t launch_scatter_ls1(const Task* d_task, uint32_t nchunks, uint64_t chu
     return hipGetLastError();
 }
 
+// Round 0 of device-described segments, in one workgroup: segments are taken
+// 1024 at a time; each lane classifies its segment (nothing, a base-case
+// group, or a task with a global model), and block scans of the nine list
+// counters give every item its place, in segment order (the same lists the
+// host builds for host-described arrays).
+constexpr uint32_t kSegQ = 9;   // groups x3, tasks, samples, blocks, leafs, models, group keys
+
+__global__ __launch_bounds__(1024) void k_seg_prepare(SegPrepare A)
+{
+    __shared__ uint64_t wsum[kSegQ][1024 / 64];
+    __shared__ uint64_t carry[kSegQ];
+    __shared__ uint64_t s_maxm;
+    __shared__ uint32_t s_err;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    if (threadIdx.x < kSegQ)
+        carry[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        s_maxm = 0;
+        s_err = A.nseg && A.off[0] != 0 ? 1u : 0u;
+    }
+    __syncthreads();
+    uint64_t my_maxm = 0;
+    uint32_t my_err = 0;
+    for (uint64_t base = 0; base < A.nseg; base += 1024) {
+        const uint64_t i = base + threadIdx.x;
+        const bool valid = i < A.nseg;
+        uint64_t lo = 0, n = 0;
+        uint32_t dt = A.dtype;
+        if (valid) {
+            lo = A.off[i];
+            const uint64_t hi = A.off[i + 1];
+            if (hi < lo)
+                my_err = 1;
+            else
+                n = hi - lo;
+            if (A.dtypes)
+                dt = A.dtypes[i];
+        }
+        const bool small = n > 1 && n <= 2ull * A.base;
+        const bool task = n > 2ull * A.base;
+        const uint32_t cls = small ? group_class((uint32_t)n) : 0u;
+        const uint64_t m = task ? sample_size(n, A.rate, A.cap) : 0;
+        const bool sampled = task && m > kSampleBlock;
+        uint64_t q[kSegQ] = {small && cls == 0 ? 1u : 0u,
+                             small && cls == 1 ? 1u : 0u,
+                             small && cls == 2 ? 1u : 0u,
+                             task ? 1u : 0u,
+                             sampled ? m : 0u,
+                             sampled ? (m + kSampleBlock - 1) / kSampleBlock : 0u,
+                             sampled ? A.leaves : 0u,
+                             task ? model_doubles(A.leaves) : 0u,
+                             small ? n : 0u};
+        uint64_t x[kSegQ];
+#pragma unroll
+        for (uint32_t j = 0; j < kSegQ; ++j) {
+            x[j] = q[j];
+#pragma unroll
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                const uint64_t y = __shfl_up(x[j], d, 64);
+                if (lane >= d)
+                    x[j] += y;
+            }
+            if (lane == 63)
+                wsum[j][wave] = x[j];
+        }
+        __syncthreads();
+        if (threadIdx.x < kSegQ) {
+            uint64_t run = carry[threadIdx.x];
+            for (uint32_t w = 0; w < 1024 / 64; ++w) {
+                const uint64_t t = wsum[threadIdx.x][w];
+                wsum[threadIdx.x][w] = run;
+                run += t;
+            }
+            carry[threadIdx.x] = run;
+        }
+        __syncthreads();
+        uint64_t off[kSegQ];
+#pragma unroll
+        for (uint32_t j = 0; j < kSegQ; ++j)
+            off[j] = wsum[j][wave] + x[j] - q[j];
+        uint64_t* keys = A.keys + lo;
+        if (small) {
+            Group g;
+            g.src = keys;
+            g.dst = keys;
+            g.start = 0;
+            g.n = (uint32_t)n;
+            g.dtype = dt;
+            A.groups[cls][off[cls]] = g;
+        }
+        if (task) {
+            Task t{};
+            t.keys = keys;
+            t.scratch = A.inplace ? keys : A.scratch + lo;
+            t.n = n;
+            t.dtype = dt;
+            t.seg = (uint32_t)i;
+            t.kind = kGlobal;
+            t.fanout = child_fanout(n, A.base, A.fanout);
+            if (A.inplace)
+                t.fanout = ip_fanout(n, t.fanout);
+            t.scale = (double)t.fanout;
+            t.leaves = A.leaves;
+            t.model = off[7];
+            A.tasks[off[3]] = t;
+            ModelJob J;
+            J.src = keys;
+            J.n = n;
+            J.m = m;
+            J.seed = A.seed;
+            J.sample_off = off[4];
+            J.model_off = off[7];
+            J.leaf_off = off[6];
+            J.leaves = A.leaves;
+            J.dtype = dt;
+            J.block0 = (uint32_t)off[5];
+            J.nblocks = sampled ? (uint32_t)((m + kSampleBlock - 1) / kSampleBlock) : 0u;
+            A.jobs[off[3]] = J;
+            my_maxm = max(my_maxm, (unsigned long long)m);
+        }
+        __syncthreads();
+    }
+    my_maxm = wave_max(my_maxm);
+    if (lane == 0)
+        atomicMax((unsigned long long*)&s_maxm, (unsigned long long)my_maxm);
+    if (my_err)
+        atomicOr(&s_err, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        RoundCtl c{};
+        c.ntasks = (uint32_t)carry[3];
+        for (uint32_t k = 0; k < kGroupClasses; ++k)
+            c.ngroups[k] = (uint32_t)carry[k];
+        c.cur.njobs = (uint32_t)carry[3];
+        c.cur.blocks = (uint32_t)carry[5];
+        c.cur.samples = carry[4];
+        c.cur.max_sample = s_maxm;
+        *A.ctl = c;
+        A.summary[0] = carry[8];
+        A.summary[1] = carry[6];
+        A.summary[2] = carry[7];
+        A.summary[3] = s_err;
+    }
+}
+
+hipError_t launch_seg_prepare(const SegPrepare& A, hipStream_t st)
+{
+    k_seg_prepare<<<1, 1024, 0, st>>>(A);
+    return hipGetLastError();
+}
+
 hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                           const double* d_models, const uint64_t* d_pos, const uint8_t* d_skip,
                           const uint32_t* d_task_flags, uint32_t tile, uint32_t max_fanout, uint32_t max_leaves,
