@@ -517,8 +517,9 @@ hipError_t launch_ip_permute(const Task* d_tasks, uint32_t ntasks, uint64_t nbuc
 {
     if (!nbuckets || !gslots)
         return hipSuccess;
-    // about one wave per 32 slots, at most 16 waves per CU
-    const uint64_t waves = std::min<uint64_t>(std::max<uint64_t>(gslots / 32, 1), 256ull * 16);
+    // about one wave per 32 slots, at most 32 waves per CU (all resident:
+    // the kernel takes 20 registers)
+    const uint64_t waves = std::min<uint64_t>(std::max<uint64_t>(gslots / 32, 1), 256ull * 32);
     const uint32_t grid = (uint32_t)((waves + 3) / 4);
     k_ip_permute<<<grid, 256, 0, st>>>(d_tasks, ntasks, nbuckets, gslots, d_bk, d_tags, d_done, d_ovf, epoch, d_ctl);
     return hipGetLastError();
