@@ -90,7 +90,7 @@ struct ls_ctx {
     // in-place rounds (LS_FLAG_INPLACE): partial counts and their scan, the
     // bucket plans, full blocks per bucket, overflow blocks, block tags and
     // read flags, the side buffer of open fragments
-    DevBuf pcnt, ppos, ipb, fullb, ovf, tags, done, sidebuf;
+    DevBuf pcnt, ppos, ipb, fullb, ovf, tags, done, sidebuf, bidx;
     uint32_t ip_epoch = 0;
     DevBuf groups[kGroupClasses];
     PinBuf pin_jobs;
@@ -685,6 +685,7 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
             TRY(ensure(C, C->fullb, (R.buckets + 1) / 2 * 8, st));
             TRY(ensure(C, C->ovf, R.buckets * kIpBlock * 8, st));
             TRY(ensure(C, C->tags, gslots * 2, st));
+            TRY(ensure(C, C->bidx, gslots * 4, st));
             TRY(ensure(C, C->sidebuf, std::max<size_t>(R.side_keys, 1) * 8, st));
             // read flags hold the epoch of the round that released the slot
             // (never 0, the value of a cleared flag)
@@ -736,7 +737,8 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
             HIPCHECK(C, launch_zero(C->fullb.p, (R.buckets + 1) / 2 * 8, st));
             HIPCHECK(C, launch_ip_frag((const Task*)C->tasks.p, nt, R.chunks, R.chunk, (const double*)C->models.p,
                                        (uint32_t*)C->cnt.p, (uint32_t*)C->pcnt.p, (uint32_t*)C->fullb.p,
-                                       (uint64_t*)C->bstat.p, (uint16_t*)C->tags.p, (uint64_t*)C->sidebuf.p,
+                                       (uint64_t*)C->bstat.p, (uint16_t*)C->tags.p, (uint32_t*)C->bidx.p,
+                                       (uint64_t*)C->sidebuf.p,
                                        R.max_fanout, R.max_leaves, flags, st));
             prof.end((double)R.nkeys * 16.0);
         } else {
@@ -768,10 +770,16 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
             // fragments and overflow blocks to the rest of each bucket
             HIPCHECK(C, launch_ip_plan((const Task*)C->tasks.p, nt, R.buckets, (const uint64_t*)C->pos.p,
                                        (const uint32_t*)C->fullb.p, (IpBucket*)C->ipb.p, st));
-            HIPCHECK(C, launch_ip_permute((const Task*)C->tasks.p, nt, R.buckets, gslots, (IpBucket*)C->ipb.p,
-                                          (const uint16_t*)C->tags.p, (uint32_t*)C->done.p, (uint64_t*)C->ovf.p,
-                                          C->ip_epoch = C->ip_epoch + 1 ? C->ip_epoch + 1 : 1u, (RoundCtl*)C->ctl.p,
-                                          st));
+            // claim words hold 2 epoch and 2 epoch + 1 of their round; once
+            // the epoch would pass 2^31 they are cleared and it starts over
+            if (++C->ip_epoch >= (1u << 31)) {
+                HIPCHECK(C, launch_zero(C->done.p, C->done.cap / 8 * 8, st));
+                C->ip_epoch = 1;
+            }
+            HIPCHECK(C, launch_ip_permute((const Task*)C->tasks.p, nt, gslots, R.chunk, (const IpBucket*)C->ipb.p,
+                                          (const uint64_t*)C->pos.p, (const uint64_t*)C->ppos.p,
+                                          (const uint16_t*)C->tags.p, (uint32_t*)C->bidx.p, (uint32_t*)C->done.p,
+                                          (uint64_t*)C->ovf.p, C->ip_epoch, (RoundCtl*)C->ctl.p, st));
             HIPCHECK(C, launch_ip_gather((const Task*)C->tasks.p, nt, R.chunks, R.chunk, R.buckets,
                                          (const uint32_t*)C->pcnt.p,
                                          (const uint64_t*)C->ppos.p, (const IpBucket*)C->ipb.p,
@@ -1209,13 +1217,13 @@ ls_status run_graph(ls_ctx* C, std::vector<Array>& arrays, hipStream_t st, const
 // not hold would end the sort with an error, never write past a buffer.
 
 // The context's device buffers, in one list (save, carve, restore, free).
-constexpr size_t kCtxBufs = 31;
+constexpr size_t kCtxBufs = 32;
 std::array<DevBuf*, kCtxBufs> ctx_bufs(ls_ctx* C)
 {
     return {&C->scratch, &C->tune, &C->models, &C->sample, &C->sample2, &C->tbest, &C->tfirst,
             &C->tnf, &C->gjobs, &C->ljobs, &C->tasks, &C->next, &C->cnt, &C->pos, &C->scantmp, &C->bstat,
             &C->skip, &C->tflags, &C->fills, &C->ctl, &C->groups[0], &C->groups[1], &C->groups[2],
-            &C->pcnt, &C->ppos, &C->ipb, &C->fullb, &C->ovf, &C->tags, &C->done, &C->sidebuf};
+            &C->pcnt, &C->ppos, &C->ipb, &C->fullb, &C->ovf, &C->tags, &C->done, &C->sidebuf, &C->bidx};
 }
 
 struct Carve {

@@ -6,7 +6,8 @@
 //                 every key to its bucket's fragment of kIpBlock keys in LDS.
 //                 A full fragment is written back into the chunk itself at a
 //                 write head that never passes the read position (Alg. 1);
-//                 the bucket of every written block is logged.  At the end of
+//                 the bucket of every written block, and its index among
+//                 the chunk's full blocks of that bucket, are logged.  At the end of
 //                 the chunk the partly filled fragments go to a side buffer
 //                 and the rest of the chunk is marked empty.  Per (bucket,
 //                 chunk) it counts keys and partial keys, and per bucket full
@@ -15,21 +16,22 @@
 //   k_ip_plan     bucket b of a task owns the range [S_b, E_b) of the final
 //                 layout; its full blocks go to the block-aligned slots
 //                 [a_b, a_b + M'_b) inside it (at most one block that does
-//                 not fit goes to an overflow block).  The slots from a_b up
-//                 to the next bucket's a are b's "area".
-//   k_ip_permute  Defragment as a parallel block permutation: waves take
-//                 unread slots from the top of an area (a read pointer r_b),
-//                 carry the block to its bucket's next free slot (a write
-//                 pointer w_b, in the same 64-bit word as r_b so that one
-//                 atomic orders both), swapping out a block not yet read.
-//                 Blocks of one bucket are interchangeable, so any free slot
-//                 of the bucket will do.
+//                 not fit goes to an overflow block).
+//   k_ip_dest     every full block's destination: the blocks of a bucket
+//                 fill its slots in chunk order, then in their order inside
+//                 a chunk (the counts' scans give where each chunk's run of
+//                 them starts), so the permutation is fixed before it runs.
+//   k_ip_permute  Defragment as a parallel block permutation: waves claim the
+//                 slots of their share one by one (one claim word per slot),
+//                 carry each block to its destination, and swap out a block
+//                 that nobody has read yet.  A slot's word is touched by at
+//                 most its reader and the one block bound for it.
 //   k_ip_gather   the partial fragments and overflow blocks fill the rest of
 //                 each bucket's range (its head before a_b and its tail after
 //                 the placed blocks).
 //
-// Extra device memory per round: one u16 tag and one u32 flag per block of
-// kIpBlock keys, a side buffer of at most min(chunk, fanout (kIpBlock - 1))
+// Extra device memory per round: one u16 tag, one u32 index / destination
+// and one u32 claim word per block of kIpBlock keys, a side buffer of at most min(chunk, fanout (kIpBlock - 1))
 // keys per chunk (a task's fanout is at most its keys / (64 kIpBlock), and
 // its chunks hold at least 64 x fanout blocks, so the side buffer is at most
 // 1/64 of the keys), one overflow block (at most 1/64 of the keys in all)
@@ -132,8 +134,8 @@ __device__ __forceinline__ IpFragLds ip_frag_lds(unsigned char* smem, uint32_t f
 
 template <uint32_t DT, bool MSD>
 __device__ void ip_frag_body(const Task& T, const SModel& M, gptr<uint64_t> keys, uint32_t n,
-                             gptr<uint16_t> tags, gptr<uint64_t> side, const IpFragLds& L, uint32_t* wsum,
-                             uint32_t* s_wh, uint32_t flags)
+                             gptr<uint16_t> tags, gptr<uint32_t> bidx, gptr<uint64_t> side, const IpFragLds& L,
+                             uint32_t* wsum, uint32_t* s_wh, uint32_t flags)
 {
     constexpr uint32_t NT = kIpThreads;
     const uint32_t f = T.fanout;
@@ -179,8 +181,10 @@ __device__ void ip_frag_body(const Task& T, const SModel& M, gptr<uint64_t> keys
                 keys[(uint64_t)(wh + L.bbase[b]) * kIpBlock + p] = L.frag[j];
         }
         for (uint32_t b = t; b < f; b += NT)
-            for (uint32_t k = 0; k < L.nfull[b]; ++k)
+            for (uint32_t k = 0; k < L.nfull[b]; ++k) {
                 tags[wh + L.bbase[b] + k] = (uint16_t)b;
+                bidx[wh + L.bbase[b] + k] = L.fullc[b] + k;
+            }
         __syncthreads();
         // keys of completed blocks go to them, the others open a fragment
 #pragma unroll
@@ -222,7 +226,7 @@ __device__ void ip_frag_body(const Task& T, const SModel& M, gptr<uint64_t> keys
 __global__ __launch_bounds__(kIpThreads) void k_ip_frag(const Task* tasks, uint32_t ntasks, uint64_t chunk,
                                                         const double* models, uint32_t* cnt, uint32_t* pcnt,
                                                         uint32_t* fullb, uint64_t* bstat, uint16_t* tags,
-                                                        uint64_t* side, uint32_t flags)
+                                                        uint32_t* bidx, uint64_t* side, uint32_t flags)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_task, s_wh;
@@ -253,13 +257,14 @@ __global__ __launch_bounds__(kIpThreads) void k_ip_frag(const Task* tasks, uint3
     const uint32_t n = (uint32_t)(min(T.n, lo + chunk) - lo);
     const gptr<uint64_t> keys = as_global(T.keys + T.start + lo);
     const gptr<uint16_t> tg = as_global(tags + ip_slot_off(T, ti) + lo / kIpBlock);
+    const gptr<uint32_t> bx = as_global(bidx + ip_slot_off(T, ti) + lo / kIpBlock);
     const gptr<uint64_t> sd = as_global(side + T.side_off + (uint64_t)lc * ip_side_keys(chunk, f));
     if (T.dtype == kF64) {
-        if (msd) ip_frag_body<kF64, true>(T, M, keys, n, tg, sd, L, wsum, &s_wh, flags);
-        else ip_frag_body<kF64, false>(T, M, keys, n, tg, sd, L, wsum, &s_wh, flags);
+        if (msd) ip_frag_body<kF64, true>(T, M, keys, n, tg, bx, sd, L, wsum, &s_wh, flags);
+        else ip_frag_body<kF64, false>(T, M, keys, n, tg, bx, sd, L, wsum, &s_wh, flags);
     } else {
-        if (msd) ip_frag_body<kU64, true>(T, M, keys, n, tg, sd, L, wsum, &s_wh, flags);
-        else ip_frag_body<kU64, false>(T, M, keys, n, tg, sd, L, wsum, &s_wh, flags);
+        if (msd) ip_frag_body<kU64, true>(T, M, keys, n, tg, bx, sd, L, wsum, &s_wh, flags);
+        else ip_frag_body<kU64, false>(T, M, keys, n, tg, bx, sd, L, wsum, &s_wh, flags);
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
@@ -277,8 +282,8 @@ __global__ __launch_bounds__(kIpThreads) void k_ip_frag(const Task* tasks, uint3
 
 hipError_t launch_ip_frag(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                           const double* d_models, uint32_t* d_cnt, uint32_t* d_pcnt, uint32_t* d_fullb,
-                          uint64_t* d_bstat, uint16_t* d_tags, uint64_t* d_side, uint32_t max_fanout,
-                          uint32_t max_leaves, uint32_t flags, hipStream_t st)
+                          uint64_t* d_bstat, uint16_t* d_tags, uint32_t* d_bidx, uint64_t* d_side,
+                          uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, hipStream_t st)
 {
     if (!total_chunks)
         return hipSuccess;
@@ -286,7 +291,7 @@ hipError_t launch_ip_frag(const Task* d_tasks, uint32_t ntasks, uint32_t total_c
         return hipErrorInvalidValue;
     const size_t smem = ip_frag_fixed_bytes(max_fanout) + model_lds_bytes(max_leaves);
     k_ip_frag<<<total_chunks, kIpThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_cnt, d_pcnt, d_fullb,
-                                                      d_bstat, d_tags, d_side, flags);
+                                                      d_bstat, d_tags, d_bidx, d_side, flags);
     return hipGetLastError();
 }
 
@@ -329,8 +334,8 @@ __global__ __launch_bounds__(256) void k_ip_plan(const Task* tasks, uint32_t nta
     const uint64_t fit = E / kIpBlock > a ? E / kIpBlock - a : 0;
     const uint64_t m = fullb[gb];
     const uint64_t placed = m < fit ? m : fit;
+    (void)a_next;
     IpBucket B;
-    B.ptr = (area & 0xffffffffull) | ((uint64_t)(uint32_t)((int64_t)a_next - 1) << 32);
     B.start = S;
     B.end = E;
     B.a = (uint32_t)a;
@@ -352,22 +357,6 @@ hipError_t launch_ip_plan(const Task* d_tasks, uint32_t ntasks, uint64_t nbucket
 
 // --------------------------------------------------------------- permute --
 
-// The key range of a task, as a wave-uniform pointer.
-__device__ __forceinline__ uint64_t* uni_keys(const Task& T)
-{
-    const uint64_t p = (uint64_t)(T.keys + T.start);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)p);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(p >> 32));
-    return (uint64_t*)((uint64_t)lo | ((uint64_t)hi << 32));
-}
-
-// Global slot where bucket gb's area starts (for spreading the waves).
-__device__ __forceinline__ uint64_t ip_area_gstart(const Task* tasks, const IpBucket* bk, uint64_t gb)
-{
-    const IpBucket& B = bk[gb];
-    return ip_slot_off(tasks[B.task], B.task) + B.area;
-}
-
 // A value every lane of the wave holds (or lane 0's), in a scalar register,
 // so that branches on it are uniform.
 __device__ __forceinline__ uint64_t ip_uni64(uint64_t v)
@@ -382,37 +371,23 @@ __device__ __forceinline__ uint32_t ip_uni32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-// Lane 0: claim the next unread slot of bucket p's area from the top (r -= 1).
-// Returns the (w, r) word before the claim; the slot is r when r >= w.
-__device__ __forceinline__ uint64_t ip_claim_read(unsigned long long* p)
+// The key range of a task, as a wave-uniform pointer.
+__device__ __forceinline__ uint64_t* uni_keys(const Task& T)
 {
-    uint64_t old = 0;
-    if (threadIdx.x % 64 == 0)
-        old = atomicAdd(p, 0xffffffff00000000ull);
-    return ip_uni64(old);
+    return (uint64_t*)ip_uni64((uint64_t)(T.keys + T.start));
 }
 
-// Lane 0: claim bucket p's next free slot (w += 1).  Returns the (w, r) word
-// before the claim; w >= dend there means the bucket's block that does not
-// fit (at most one per bucket, so w ends at dend + 1 or below).  One atomic
-// add per claim: a compare-and-swap loop would retry under the contention
-// of thousands of waves writing into few buckets.
-__device__ __forceinline__ uint64_t ip_claim_write(unsigned long long* p)
-{
-    uint64_t old = 0;
-    if (threadIdx.x % 64 == 0)
-        old = atomicAdd(p, 1ull);
-    return ip_uni64(old);
-}
-
-// Lane 0: wait (bounded) until the reader that claimed a slot has its block in
-// registers; a wait that runs out raises the control block's overflow bit 2
-// (the sort then reports an error) instead of hanging.
-__device__ __forceinline__ void ip_wait_released(uint32_t* flag, uint32_t epoch, RoundCtl* ctl)
+// Lane 0: wait (bounded) until the reader that claimed a slot has its block
+// in registers (the slot's word holds `rel`); a wait that runs out raises
+// the control block's overflow bit 2 (the sort then reports an error)
+// instead of hanging.  The only hazard is the reader's load against the
+// waiter's later store to the same slot, so plain atomic loads do: no
+// acquire (on this GPU an agent-scope acquire invalidates the L2).
+__device__ __forceinline__ void ip_wait_released(uint32_t* flag, uint32_t rel, RoundCtl* ctl)
 {
     if (threadIdx.x % 64 == 0) {
         uint32_t spins = 0;
-        while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != rel) {
             if (++spins >= kIpSpinLimit) {
                 atomicOr(&ctl->overflow, 2u);
                 break;
@@ -422,106 +397,155 @@ __device__ __forceinline__ void ip_wait_released(uint32_t* flag, uint32_t epoch,
     }
 }
 
-// Lane 0: release a slot that was read (its block is in registers).
-__device__ __forceinline__ void ip_release(uint32_t* flag, uint32_t epoch)
+// Release a slot that was read: once its block is in registers (every load
+// of the wave has returned), the word says so.  Nothing written before needs
+// to be seen by the waiter, so no fence (an agent-scope release would write
+// the L2 back).
+__device__ __forceinline__ void ip_release(uint32_t* flag, uint32_t rel)
 {
+    asm volatile("" ::: "memory");
     __builtin_amdgcn_s_waitcnt(0);
-    __threadfence();
+    asm volatile("" ::: "memory");
     if (threadIdx.x % 64 == 0)
-        __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(flag, rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Every wave takes an equal share of the round's global slots and reads the
-// areas of the buckets that overlap it, top down, until each is exhausted;
-// every block it reads is carried to its bucket (see the file comment).  The
-// lane l of a wave holds key l of the block in hand.  All control flow is on
-// wave-uniform values.
-__global__ __launch_bounds__(256) void k_ip_permute(const Task* tasks, uint32_t ntasks, uint64_t nbuckets,
-                                                    uint64_t gslots, IpBucket* bk, const uint16_t* tags,
-                                                    uint32_t* done, uint64_t* ovf, uint32_t epoch,
-                                                    RoundCtl* ctl)
+// The task whose slot range holds global slot g: the last task whose slots
+// start at or before it (tasks are laid out with increasing slot offsets;
+// one slot between tasks belongs to none).
+__device__ __forceinline__ uint32_t find_task_of_slot(const Task* tasks, uint32_t ntasks, uint64_t g)
+{
+    uint32_t lo = 0, hi = ntasks;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ip_slot_off(tasks[mid], mid) <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Destination of every full block, in place of its index: block j of bucket
+// b written by chunk c goes to slot a_b + (full blocks of b in chunks before
+// c) + j, the full blocks of earlier chunks coming from the scans of the key
+// and partial-key counts; past the bucket's placed blocks it is the block
+// that does not fit.  Slots without a full block get kIpNoDest.
+__global__ __launch_bounds__(256) void k_ip_dest(const Task* tasks, uint32_t ntasks, uint64_t gslots, uint64_t chunk,
+                                                 const IpBucket* bk, const uint64_t* pos, const uint64_t* ppos,
+                                                 const uint16_t* tags, uint32_t* bidx)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= gslots)
+        return;
+    const uint32_t ti = find_task_of_slot(tasks, ntasks, g);
+    const Task& T = tasks[ti];
+    const uint64_t s = g - ip_slot_off(T, ti);
+    if (s >= T.n / kIpBlock)
+        return;                         // the slot between two tasks: never read
+    const uint16_t tag = tags[g];
+    uint32_t d = kIpNoDest;
+    if (tag != kIpEmpty) {
+        const uint64_t c = s / (chunk / kIpBlock);
+        const uint64_t e0 = T.cnt_off + (uint64_t)tag * T.nchunks, e = e0 + c;
+        const uint64_t before = ((pos[e] - pos[e0]) - (ppos[e] - ppos[e0])) / kIpBlock;
+        const IpBucket& B = bk[T.bucket_off + tag];
+        const uint64_t k = before + bidx[g];
+        d = k < (uint64_t)(B.dend - B.a) ? (uint32_t)(B.a + k) : (kIpOvf | tag);
+    }
+    bidx[g] = d;
+}
+
+// Lane 0 swaps a slot's claim word to `cl`; the word it held, in a scalar.
+__device__ __forceinline__ uint32_t ip_claim(uint32_t* w, uint32_t cl)
+{
+    uint32_t old = 0;
+    if (threadIdx.x % 64 == 0)
+        old = __hip_atomic_exchange(w, cl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return ip_uni32(old);
+}
+
+// Every wave takes an equal share of the round's global slots and claims
+// each of them in turn; a slot already claimed this round (as some block's
+// destination) is skipped.  The block of a claimed slot is loaded, the slot
+// released, and the block carried to its destination: if that slot was
+// claimed by its reader, the wave waits for the release (bounded) and
+// stores; if it is unclaimed, the wave claims it, swaps its block out and
+// carries that one on.  Each destination is the destination of one block
+// only, so a slot's word is swapped by at most its reader and that one
+// writer: claim words hold 2 epoch (claimed) and 2 epoch + 1 (released);
+// words of earlier rounds are smaller.  No word is shared by more than two
+// waves, so there is no queue on any address.  The lane l of a wave holds
+// key l of the block in hand; all control flow is on wave-uniform values.
+__global__ __launch_bounds__(256) void k_ip_permute(const Task* tasks, uint32_t ntasks, uint64_t gslots,
+                                                    const uint32_t* dest, uint32_t* word, uint64_t* ovf,
+                                                    uint32_t epoch, RoundCtl* ctl)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t nw = (uint64_t)gridDim.x * (256 / 64);
     const uint64_t w = (uint64_t)blockIdx.x * (256 / 64) + (threadIdx.x >> 6);
     const uint64_t seg_lo = gslots * w / nw, seg_hi = gslots * (w + 1) / nw;
-    if (seg_lo >= seg_hi || !nbuckets)
+    if (seg_lo >= seg_hi)
         return;
-    // first bucket whose area reaches past seg_lo: the last area starting at
-    // or before it
-    uint64_t lo = 0, hi = nbuckets;
-    while (hi - lo > 1) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (ip_area_gstart(tasks, bk, mid) <= seg_lo) lo = mid; else hi = mid;
-    }
-    lo = ip_uni64(lo);
-    const gptr<const uint16_t> gtags = as_global(tags);
-    for (uint64_t gb = lo; gb < nbuckets && ip_uni64(ip_area_gstart(tasks, bk, gb)) < seg_hi; ++gb) {
-        const uint32_t ti = ip_uni32(bk[gb].task);
+    const uint32_t cl = 2u * epoch, rel = 2u * epoch + 1u;
+    const gptr<const uint32_t> gdest = as_global(dest);
+    uint32_t ti = ip_uni32(find_task_of_slot(tasks, ntasks, seg_lo));
+    for (uint64_t g = seg_lo; g < seg_hi; ++g) {
+        while (ti + 1 < ntasks && ip_uni64(ip_slot_off(tasks[ti + 1], ti + 1)) <= g)
+            ++ti;
         const uint64_t soff = ip_uni64(ip_slot_off(tasks[ti], ti));
-        const uint64_t boff = ip_uni64(tasks[ti].bucket_off);
+        const uint64_t nslots = ip_uni64(tasks[ti].n / kIpBlock);
+        if (g - soff >= nslots)
+            continue;                   // the slot between two tasks
+        if (ip_claim(word + g, cl) >= cl)
+            continue;                   // taken this round as a destination
         const gptr<uint64_t> base = as_global(uni_keys(tasks[ti]));
-        // slots at or above dend are never written: they are read whatever w is
-        const int32_t rd_end = (int32_t)ip_uni32(bk[gb].dend);
-        bool more = true;
-        while (more) {
-            const uint64_t old = ip_claim_read((unsigned long long*)&bk[gb].ptr);
-            const int32_t w_old = (int32_t)(uint32_t)old, r_old = (int32_t)(uint32_t)(old >> 32);
-            if (r_old < min(w_old, rd_end)) {
-                more = false;
-            } else {
-                const uint64_t s = (uint32_t)r_old;
-                const uint32_t tg0 = ip_uni32(gtags[soff + s]);
-                uint64_t key = 0;
-                if (tg0 != kIpEmpty)
-                    key = base[s * kIpBlock + lane];
-                ip_release(done + soff + s, epoch);
-                uint64_t d = boff + tg0;
-                bool carrying = tg0 != kIpEmpty;
-                while (carrying) {
-                    const uint64_t o2 = ip_claim_write((unsigned long long*)&bk[d].ptr);
-                    if ((uint32_t)o2 >= ip_uni32(bk[d].dend)) {
-                        // the bucket's block that does not fit
-                        ovf[d * kIpBlock + lane] = key;
-                        carrying = false;
-                    } else {
-                        const int32_t w2 = (int32_t)(uint32_t)o2, r2 = (int32_t)(uint32_t)(o2 >> 32);
-                        const uint64_t tslot = (uint32_t)w2;
-                        if (r2 < w2) {
-                            // a reader has claimed the slot: wait until it holds the block
-                            ip_wait_released(done + soff + tslot, epoch, ctl);
-                            base[tslot * kIpBlock + lane] = key;
-                            carrying = false;
-                        } else {
-                            // an unread slot: swap its block out
-                            const uint32_t tg2 = ip_uni32(gtags[soff + tslot]);
-                            uint64_t k2 = 0;
-                            if (tg2 != kIpEmpty)
-                                k2 = base[tslot * kIpBlock + lane];
-                            __builtin_amdgcn_s_waitcnt(0);
-                            base[tslot * kIpBlock + lane] = key;
-                            key = k2;
-                            d = boff + tg2;
-                            carrying = tg2 != kIpEmpty;
-                        }
-                    }
-                }
+        const uint64_t bucket_off = ip_uni64(tasks[ti].bucket_off);
+        uint32_t d = ip_uni32(gdest[g]);
+        uint64_t key = 0;
+        if (d != kIpNoDest)
+            key = base[(g - soff) * kIpBlock + lane];
+        ip_release(word + g, rel);
+        bool carrying = d != kIpNoDest && d != (uint32_t)(g - soff);   // (a block already in place stays)
+        while (carrying) {
+            if (d & kIpOvf) {
+                // the bucket's block that does not fit
+                ovf[(bucket_off + (d & ~kIpOvf)) * kIpBlock + lane] = key;
+                break;
             }
+            const uint64_t dg = soff + d;
+            const uint32_t old = ip_claim(word + dg, cl);
+            if (old >= cl) {
+                // its reader has it (or had it): store once it is released
+                if (old != rel)
+                    ip_wait_released(word + dg, rel, ctl);
+                base[(uint64_t)d * kIpBlock + lane] = key;
+                break;
+            }
+            // unclaimed: swap its block out and carry that one
+            const uint32_t d2 = ip_uni32(gdest[dg]);
+            uint64_t k2 = 0;
+            if (d2 != kIpNoDest)
+                k2 = base[(uint64_t)d * kIpBlock + lane];
+            __builtin_amdgcn_s_waitcnt(0);
+            base[(uint64_t)d * kIpBlock + lane] = key;
+            key = k2;
+            d = d2;
+            carrying = d2 != kIpNoDest;
         }
     }
 }
 
-hipError_t launch_ip_permute(const Task* d_tasks, uint32_t ntasks, uint64_t nbuckets, uint64_t gslots,
-                             IpBucket* d_bk, const uint16_t* d_tags, uint32_t* d_done, uint64_t* d_ovf,
+hipError_t launch_ip_permute(const Task* d_tasks, uint32_t ntasks, uint64_t gslots, uint64_t chunk,
+                             const IpBucket* d_bk, const uint64_t* d_pos, const uint64_t* d_ppos,
+                             const uint16_t* d_tags, uint32_t* d_bidx, uint32_t* d_word, uint64_t* d_ovf,
                              uint32_t epoch, RoundCtl* d_ctl, hipStream_t st)
 {
-    if (!nbuckets || !gslots)
+    if (!gslots || !ntasks)
         return hipSuccess;
-    // about one wave per 32 slots, at most 32 waves per CU (all resident:
-    // the kernel takes 20 registers)
+    k_ip_dest<<<(uint32_t)((gslots + 255) / 256), 256, 0, st>>>(d_tasks, ntasks, gslots, chunk, d_bk, d_pos, d_ppos,
+                                                               d_tags, d_bidx);
+    // about one wave per 32 slots, at most 32 waves per CU (all resident)
     const uint64_t waves = std::min<uint64_t>(std::max<uint64_t>(gslots / 32, 1), 256ull * 32);
     const uint32_t grid = (uint32_t)((waves + 3) / 4);
-    k_ip_permute<<<grid, 256, 0, st>>>(d_tasks, ntasks, nbuckets, gslots, d_bk, d_tags, d_done, d_ovf, epoch, d_ctl);
+    k_ip_permute<<<grid, 256, 0, st>>>(d_tasks, ntasks, gslots, d_bidx, d_word, d_ovf, epoch, d_ctl);
     return hipGetLastError();
 }
 

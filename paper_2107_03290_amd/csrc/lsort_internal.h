@@ -158,14 +158,17 @@ __host__ __device__ inline uint64_t ip_side_keys(uint64_t chunk, uint32_t fanout
 
 // A bucket of an in-place round: its range [start, end) in the task's final
 // layout; its full blocks go to the slots [a, dend) (one more that does not
-// fit goes to an overflow block); its area of slots to read out starts at
-// `area`; `ptr` holds the write pointer w (low 32 bits) and the read pointer
-// r (high 32 bits, signed) of the block permutation.
+// fit goes to an overflow block).
 struct IpBucket {
-    uint64_t ptr;
     uint64_t start, end;
     uint32_t a, area, dend, full, task, pad;
 };
+
+// Destination of a block slot in the permutation: a slot of the task, or
+// kIpOvf | b for bucket b's block that does not fit, or kIpNoDest for a slot
+// that holds no full block.
+constexpr uint32_t kIpOvf = 0x80000000u;
+constexpr uint32_t kIpNoDest = 0xffffffffu;
 
 // Sizes of the running round, copied from the control block when the round
 // starts.  In graph mode the kernels are launched with upper-bound grids and
@@ -402,19 +405,23 @@ hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_c
                           uint32_t flags, const LiveCounts* live, hipStream_t st);
 // In-place round (LS_FLAG_INPLACE): fragments written back into the chunks
 // (cnt: keys, pcnt: partial keys per (bucket, chunk); fullb: full blocks per
-// bucket, cleared by the caller; tags: the bucket of every block slot;
-// side: ip_side_keys(chunk, fanout) keys per chunk of a task from its
-// side_off), the plan of each
-// bucket's slots, the block permutation and the gather of the rest.
+// bucket, cleared by the caller; tags: the bucket of every block slot; bidx:
+// the block's index among its bucket's full blocks of its chunk; side:
+// ip_side_keys(chunk, fanout) keys per chunk of a task from its side_off),
+// the plan of each bucket's slots, the block permutation (pos, ppos: the
+// scans of cnt and pcnt; bidx becomes each slot's destination; word: one
+// claim word per slot, in which `epoch` (never 0, larger every round) marks
+// this round) and the gather of the rest.
 hipError_t launch_ip_frag(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                           const double* d_models, uint32_t* d_cnt, uint32_t* d_pcnt, uint32_t* d_fullb,
-                          uint64_t* d_bstat, uint16_t* d_tags, uint64_t* d_side, uint32_t max_fanout,
-                          uint32_t max_leaves, uint32_t flags, hipStream_t st);
+                          uint64_t* d_bstat, uint16_t* d_tags, uint32_t* d_bidx, uint64_t* d_side,
+                          uint32_t max_fanout, uint32_t max_leaves, uint32_t flags, hipStream_t st);
 size_t ip_frag_lds_bytes(uint32_t fanout, uint32_t leaves);
 hipError_t launch_ip_plan(const Task* d_tasks, uint32_t ntasks, uint64_t nbuckets, const uint64_t* d_pos,
                           const uint32_t* d_fullb, IpBucket* d_bk, hipStream_t st);
-hipError_t launch_ip_permute(const Task* d_tasks, uint32_t ntasks, uint64_t nbuckets, uint64_t gslots,
-                             IpBucket* d_bk, const uint16_t* d_tags, uint32_t* d_done, uint64_t* d_ovf,
+hipError_t launch_ip_permute(const Task* d_tasks, uint32_t ntasks, uint64_t gslots, uint64_t chunk,
+                             const IpBucket* d_bk, const uint64_t* d_pos, const uint64_t* d_ppos,
+                             const uint16_t* d_tags, uint32_t* d_bidx, uint32_t* d_word, uint64_t* d_ovf,
                              uint32_t epoch, RoundCtl* d_ctl, hipStream_t st);
 hipError_t launch_ip_gather(const Task* d_tasks, uint32_t ntasks, uint32_t total_chunks, uint64_t chunk,
                             uint64_t nbuckets, const uint32_t* d_pcnt, const uint64_t* d_ppos, const IpBucket* d_bk,
