@@ -507,6 +507,48 @@ def kernel_class(name: str):
     return None
 
 
+SQ_COLUMNS = ("SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_INSTS_LDS",
+              "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS", "SQ_WAIT_ANY", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+              "SQ_INSTS_SALU", "SQ_ACTIVE_INST_VALU")
+
+
+def summarize_sq(args):
+    """profiles/sq_counters_<workload>.txt from the databases of two rocprofv3
+    --pmc passes (8 SQ counters each): per kernel the counters summed over its
+    dispatches, and the ratios that say what bounds it."""
+    import sqlite3
+    per = {}
+    for pi, db in enumerate(args.summarize_sq):
+        con = sqlite3.connect(db)
+        for name, cname, v in con.execute("select name, counter_name, counter_value from pmc_events"):
+            short = name.split("(")[0].replace("void ", "").replace("lsort::", "")
+            if kernel_class(name) in (None, "upload", "scan") or (pi and cname == "SQ_WAVES"):
+                continue    # (both passes count the waves: the first one's are kept)
+            d = per.setdefault(short, {})
+            d[cname] = d.get(cname, 0.0) + v
+    lines = ["# rocprofv3 SQ counters: %s" % args.workload_name, "",
+             "commands (two passes, 8 SQ counters each; sums over every dispatch of the run):"]
+    lines += ["  " + c for c in args.sq_commands if c]
+    lines += ["", "%-30s" % "kernel" + "".join("%14s" % c.replace("SQ_", "")[:13] for c in SQ_COLUMNS)]
+    for k in sorted(per, key=lambda k: -per[k].get("SQ_WAVE_CYCLES", 0.0)):
+        d = per[k]
+        lines.append("%-30s" % k[:30] + "".join("%14.3g" % d.get(c, 0.0) for c in SQ_COLUMNS))
+    lines += ["", "derived (per kernel):"]
+    for k in sorted(per, key=lambda k: -per[k].get("SQ_WAVE_CYCLES", 0.0)):
+        d = per[k]
+        w = d.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+        lds = d.get("SQ_INSTS_LDS", 0.0) or 1.0
+        lines.append("  %-28s VALU/LDS %.2f, bank-conflict cycles per LDS instruction %.2f, any wait %.0f%% and "
+                     "LDS-issue wait %.0f%% of wave cycles, VALU instructions per wave %.0f" % (
+                         k[:28], d.get("SQ_INSTS_VALU", 0.0) / lds, d.get("SQ_LDS_BANK_CONFLICT", 0.0) / lds,
+                         100 * d.get("SQ_WAIT_ANY", 0.0) / w, 100 * d.get("SQ_WAIT_INST_LDS", 0.0) / w,
+                         d.get("SQ_INSTS_VALU", 0.0) / (d.get("SQ_WAVES", 0.0) or 1.0)))
+    path = os.path.join(ROOT, "profiles", "sq_counters_%s.txt" % args.workload_name)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", path)
+
+
 def summarize_profiles(args):
     """Turn rocprofv3 databases (a kernel trace, and optionally one FETCH_SIZE
     and one WRITE_SIZE pass) of a bench run into the text summaries kept in
@@ -589,6 +631,8 @@ def main():
     ap.add_argument("--summarize-trace", help="rocprofv3 database of a --kernel-trace run of this script")
     ap.add_argument("--summarize-fetch", help="rocprofv3 database of a --pmc FETCH_SIZE run")
     ap.add_argument("--summarize-write", help="rocprofv3 database of a --pmc WRITE_SIZE run")
+    ap.add_argument("--summarize-sq", nargs=2, help="rocprofv3 databases of the two SQ counter passes")
+    ap.add_argument("--sq-commands", nargs=2, default=["", ""])
     ap.add_argument("--workload-name", default="mixed_u64")
     ap.add_argument("--traffic-kernel", default="scatter")
     ap.add_argument("--copy-bytes", type=float, default=8e9)
@@ -620,8 +664,11 @@ def main():
     ap.add_argument("--graph", choices=("on", "off"), default="off",
                     help="served workload: run requests and batches of up to 2^22 keys as graph replays")
     args = ap.parse_args()
+    if args.summarize_sq:
+        summarize_sq(args)
     if args.summarize_trace:
         summarize_profiles(args)
+    if args.summarize_sq or args.summarize_trace:
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
