@@ -49,6 +49,8 @@ constexpr uint32_t kIpKpt = 4;
 constexpr uint32_t kIpTile = kIpThreads * kIpKpt;
 constexpr uint16_t kIpEmpty = 0xffffu;
 constexpr uint32_t kIpSpinLimit = 1u << 22;
+// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt left at their maximum
+constexpr int kIpWaitVmcnt0 = 0x0F70;
 
 // Global slot of slot s of task i: tasks of a round occupy disjoint slot
 // ranges floor(cnt_base / B) + i + [0, n / B).
@@ -142,13 +144,27 @@ __device__ void ip_frag_body(const Task& T, const SModel& M, gptr<uint64_t> keys
     const double scale = T.scale;
     const int32_t offset = (int32_t)T.offset;
     const uint32_t t = threadIdx.x;
+    // the next tile's keys are loaded while this tile is processed: the
+    // blocks a tile writes go below the keys read so far, so below the next
+    // tile (Alg. 1's invariant), and the prefetched keys are still unread
+    uint64_t nxt[kIpKpt];
+#pragma unroll
+    for (uint32_t u = 0; u < kIpKpt; ++u) {
+        const uint32_t i = u * NT + t;
+        nxt[u] = i < n ? keys[i] : 0;
+    }
     for (uint32_t base = 0; base < n; base += kIpTile) {
         uint64_t raw[kIpKpt];
         uint32_t bk[kIpKpt], rk[kIpKpt];
 #pragma unroll
-        for (uint32_t u = 0; u < kIpKpt; ++u) {
-            const uint32_t i = base + u * NT + t;
-            raw[u] = i < n ? keys[i] : 0;
+        for (uint32_t u = 0; u < kIpKpt; ++u)
+            raw[u] = nxt[u];
+        if (base + kIpTile < n) {
+#pragma unroll
+            for (uint32_t u = 0; u < kIpKpt; ++u) {
+                const uint32_t i = base + kIpTile + u * NT + t;
+                nxt[u] = i < n ? keys[i] : 0;
+            }
         }
 #pragma unroll
         for (uint32_t u = 0; u < kIpKpt; ++u) {
@@ -174,6 +190,9 @@ __device__ void ip_frag_body(const Task& T, const SModel& M, gptr<uint64_t> keys
         __syncthreads();
         const uint32_t newblocks = block_scan_u32(L.nfull, L.bbase, f, wsum);
         const uint32_t wh = *s_wh;
+        // the next tile's loads are done by now: wait for them before this
+        // tile's stores (vmcnt counts both), not at the loop's back edge
+        __builtin_amdgcn_s_waitcnt(kIpWaitVmcnt0);
         // the open fragment of a bucket that completes a block starts it
         for (uint32_t j = t; j < f * kIpBlock; j += NT) {
             const uint32_t b = j / kIpBlock, p = j % kIpBlock;
