@@ -75,3 +75,37 @@ def test_mixed_u64_1e9_properties(S):
             le += int(np.count_nonzero(c <= v))
         assert lt <= int(p) < le, (int(p), int(v))
     assert S.last_stats()["seams_repaired"] == 0
+
+
+def test_mixed_u64_1e9_in_place_properties():
+    # the in-place rounds at the full size, by the same properties, and the
+    # device memory a fresh context holds afterwards against the keys' 8 GB
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n = 1_000_000_000
+    a = W.mixed_u64(n, seed=3)
+    fp_in = fingerprint_chunked(a)
+    t = upload(a)
+    s = ls.Sorter(0)
+    try:
+        s.sort_(t, ls.params(flags=ls.FLAG_INPLACE))
+        torch.cuda.synchronize()
+        held = s.device_bytes()
+    finally:
+        s.close()
+    got = download(t)
+    del t
+    torch.cuda.empty_cache()
+    print("in place, 1e9 keys: context holds %.1f MB (%.2f%% of the keys)" % (held / 1e6, 100.0 * held / (8 * n)))
+    assert held <= 0.10 * 8 * n
+    assert is_sorted_words(got)
+    assert fingerprint_chunked(got) == fp_in
+    r = np.random.default_rng(12)
+    for p in np.concatenate([[0, n - 1, n // 2], r.integers(0, n, size=4)]):
+        v = got[int(p)]
+        lt = le = 0
+        for lo in range(0, n, 1 << 27):
+            c = a[lo:lo + (1 << 27)]
+            lt += int(np.count_nonzero(c < v))
+            le += int(np.count_nonzero(c <= v))
+        assert lt <= int(p) < le, (int(p), int(v))
