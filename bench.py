@@ -751,6 +751,21 @@ def main():
     value = n * K / (gpu_ms / 1e3)
 
     prof = S.profile()
+    roof = roofline(prof, wname)
+    # reference rate for the roofline: the runtime's device-to-device copy of
+    # the same n * 8 bytes (read and written once, as the scatter does),
+    # timed after the timed region
+    cms = []
+    for _ in range(3):
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        work[0].copy_(pristine)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        cms.append(c0.elapsed_time(c1))
+    copy_gbs = 2.0 * n * 8 / (min(cms) / 1e3) / 1e9
+    roof["copy_GBps"] = copy_gbs
+    roof["frac_of_copy"] = roof["achieved"] / copy_gbs
     line = {
         "metric": METRIC,
         "value": value,
@@ -767,7 +782,7 @@ def main():
         "config": {"workload": wname, "n": n, "fanout": p.fanout, "leaves": p.leaves,
                    "tile": p.tile or "auto (4096; 8192 in rounds of >= 2^25 keys)",
                    "base_threshold": p.base_threshold, "sample_rate": p.sample_rate, "sample_cap": p.sample_cap},
-        "roofline": roofline(prof, wname),
+        "roofline": roof,
         "kernel_ms_per_step": breakdown,
         "kernel_GBps": gbps,
         "kernel_ms_source": "%d untimed steps after the warm-up with every kernel class timed; the timed "
