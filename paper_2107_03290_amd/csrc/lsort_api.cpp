@@ -533,7 +533,7 @@ void prepare(std::vector<Array>& arrays, void* scratch, const Params& P, bool ms
         if (a.n <= 1)
             continue;
         if (a.n <= 2ull * P.base) {
-            B.groups0[group_class((uint32_t)a.n)].push_back(Group{a.keys, a.keys, 0, (uint32_t)a.n, a.dtype});
+            B.groups0[group_class((uint32_t)a.n)].push_back(Group{a.keys, a.keys, 0, (uint32_t)a.n, a.dtype, ~0ull, 0});
             B.group0_keys += a.n;
             continue;
         }

@@ -34,6 +34,8 @@ constexpr uint64_t kSign = 0x8000000000000000ull;
 constexpr uint64_t kSkipBit = 0x8000000000000000ull;
 constexpr uint32_t kNoScatter = 1u;
 constexpr uint32_t kFlagNonMonotone = 0x4u;   // LS_FLAG_NONMONOTONE
+// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt left at their maximum
+constexpr int kWaitVmcnt0 = 0x0F70;
 
 // ------------------------------------------------------------------ keys --
 

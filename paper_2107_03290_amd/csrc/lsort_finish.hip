@@ -42,15 +42,17 @@ __host__ __device__ constexpr size_t base_lds_bytes()
 // in flight while the workgroup waits on LDS.
 __device__ __forceinline__ Group group_at(const Group* groups, uint32_t i)
 {
-    static_assert(sizeof(Group) == 32, "four words");
-    const gptr<const uint64_t> w = as_global(reinterpret_cast<const uint64_t*>(groups) + 4ull * i);
-    const uint64_t a = w[0], b = w[1], c = w[2], d = w[3];
+    static_assert(sizeof(Group) == 48, "six words");
+    const gptr<const uint64_t> w = as_global(reinterpret_cast<const uint64_t*>(groups) + 6ull * i);
+    const uint64_t a = w[0], b = w[1], c = w[2], d = w[3], lo = w[4], hi = w[5];
     Group G;
     G.src = reinterpret_cast<const uint64_t*>(a);
     G.dst = reinterpret_cast<uint64_t*>(b);
     G.start = c;
     G.n = (uint32_t)d;
     G.dtype = (uint32_t)(d >> 32);
+    G.lo = lo;
+    G.hi = hi;
     return G;
 }
 
@@ -183,25 +185,34 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         const uint32_t dt = uni32(G.dtype);
         if (n <= CAP) {     // larger groups are never produced by classify; keeps LDS in bounds
             uint64_t o[KPT];
-            uint64_t lo = ~0ull, hi = 0;
+            // the range of the group's order words: given by the partition
+            // that formed the group, else reduced here
+            uint64_t lo = uni32((uint32_t)G.lo) | ((uint64_t)uni32((uint32_t)(G.lo >> 32)) << 32);
+            uint64_t hi = uni32((uint32_t)G.hi) | ((uint64_t)uni32((uint32_t)(G.hi >> 32)) << 32);
+            const bool known = lo <= hi;
 #pragma unroll
-            for (uint32_t k = 0; k < KPT; ++k) {
-                const uint32_t i = k * NT + t;
+            for (uint32_t k = 0; k < KPT; ++k)
                 o[k] = to_ord(raw[k], dt);
-                if (k * NT < n && i < n) {
-                    lo = o[k] < lo ? o[k] : lo;
-                    hi = o[k] > hi ? o[k] : hi;
-                }
-            }
+            if (!known) {
+                lo = ~0ull;
+                hi = 0;
 #pragma unroll
-            for (uint32_t d = 32; d > 0; d >>= 1) {
-                const uint64_t a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
-                lo = a < lo ? a : lo;
-                hi = b > hi ? b : hi;
-            }
-            if (lane == 0) {
-                s_lo[wave] = lo;
-                s_hi[wave] = hi;
+                for (uint32_t k = 0; k < KPT; ++k) {
+                    if (k * NT < n && k * NT + t < n) {
+                        lo = o[k] < lo ? o[k] : lo;
+                        hi = o[k] > hi ? o[k] : hi;
+                    }
+                }
+#pragma unroll
+                for (uint32_t d = 32; d > 0; d >>= 1) {
+                    const uint64_t a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
+                    lo = a < lo ? a : lo;
+                    hi = b > hi ? b : hi;
+                }
+                if (lane == 0) {
+                    s_lo[wave] = lo;
+                    s_hi[wave] = hi;
+                }
             }
             // at least two slots, so that the shift below stays under 64
             const uint32_t nslots = pow2_at_least(n < 4 ? 2u : (n + 1) / 2);
@@ -212,10 +223,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
             if (t == 0)
                 s_slow = 0;
             __syncthreads();
+            if (!known) {
 #pragma unroll
-            for (uint32_t w = 0; w < NW; ++w) {
-                lo = s_lo[w] < lo ? s_lo[w] : lo;
-                hi = s_hi[w] > hi ? s_hi[w] : hi;
+                for (uint32_t w = 0; w < NW; ++w) {
+                    lo = s_lo[w] < lo ? s_lo[w] : lo;
+                    hi = s_hi[w] > hi ? s_hi[w] : hi;
+                }
             }
             if (lo == hi) {     // one value: already in order
 #pragma unroll

@@ -49,8 +49,6 @@ constexpr uint32_t kIpKpt = 4;
 constexpr uint32_t kIpTile = kIpThreads * kIpKpt;
 constexpr uint16_t kIpEmpty = 0xffffu;
 constexpr uint32_t kIpSpinLimit = 1u << 22;
-// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt left at their maximum
-constexpr int kIpWaitVmcnt0 = 0x0F70;
 
 // Global slot of slot s of task i: tasks of a round occupy disjoint slot
 // ranges floor(cnt_base / B) + i + [0, n / B).
@@ -192,7 +190,7 @@ __device__ void ip_frag_body(const Task& T, const SModel& M, gptr<uint64_t> keys
         const uint32_t wh = *s_wh;
         // the next tile's loads are done by now: wait for them before this
         // tile's stores (vmcnt counts both), not at the loop's back edge
-        __builtin_amdgcn_s_waitcnt(kIpWaitVmcnt0);
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         // the open fragment of a bucket that completes a block starts it
         for (uint32_t j = t; j < f * kIpBlock; j += NT) {
             const uint32_t b = j / kIpBlock, p = j % kIpBlock;

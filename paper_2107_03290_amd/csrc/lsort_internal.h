@@ -64,6 +64,10 @@ struct Group {
     uint64_t start;       // of dst, relative to its array (0: no seam to check)
     uint32_t n;
     uint32_t dtype;
+    // smallest and largest order word of the group's keys when known (the
+    // partition's per-bucket min and max); lo > hi: not known
+    uint64_t lo;
+    uint64_t hi;
 };
 
 // The three size-class lists of groups (device pointers, passed by value).

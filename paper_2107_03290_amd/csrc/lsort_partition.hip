@@ -523,7 +523,8 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
     cidx[2] = reinterpret_cast<uint32_t*>(prv);           // prv is dead once leaders are known
     uint32_t* tidx = cidx[1] + f;
     uint32_t* fidx = tidx + f;
-    uint8_t* kind = reinterpret_cast<uint8_t*>(fidx + f);
+    int32_t* ldr = reinterpret_cast<int32_t*>(fidx + f);   // group leader of each bucket
+    uint8_t* kind = reinterpret_cast<uint8_t*>(ldr + f);
     __shared__ uint32_t ws_m[5][17];
     __shared__ int32_t ws_i[17];
     __shared__ uint32_t s_gb[kGroupClasses], s_tb, s_fb, s_noprog, s_nfb, s_over;
@@ -572,6 +573,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
         }
         const bool brk = k != kEmpty && (lead || k != kSmall);
         nxt[f - 1 - b] = brk ? (int32_t)b : kNone;
+        ldr[b] = brk ? (int32_t)b : -1;
         const uint64_t sz = bst[b + 1] - bst[b];
         tidx[b] = k == kBig ? 1u : 0u;
         fidx[b] = k == kFillB ? (uint32_t)((sz + kFillPiece - 1) / kFillPiece) : 0u;
@@ -611,6 +613,7 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
             kind[b] |= kLead;
     __syncthreads();
     block_scan_op<int32_t>(nxt, f, kNone, MinI32(), ws_i);   // nxt[f-1-b]: first breaker after b
+    block_scan_op<int32_t>(ldr, f, -1, MaxI32(), ws_i);      // ldr[b]: last breaker before b
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
         uint32_t c0 = 0, c1 = 0, c2 = 0;
         if (kind[b] & kLead) {
@@ -669,6 +672,10 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
             G.start = T.start + bst[b];
             G.n = (uint32_t)((e == kNone ? T.n : bst[e]) - bst[b]);
             G.dtype = T.dtype;
+            // the group's range: its first bucket's min and max here, the
+            // group's other buckets fold theirs in below
+            G.lo = bstat[2 * ((uint64_t)T.bucket_off + b)];
+            G.hi = bstat[2 * ((uint64_t)T.bucket_off + b) + 1];
             const uint32_t c = G.n <= kGroupClassCap[0] ? 0u : (G.n <= kGroupClassCap[1] ? 1u : 2u);
             groups.g[c][s_gb[c] + cidx[c][b]] = G;
         } else if (k == kBig) {
@@ -709,6 +716,28 @@ __global__ __launch_bounds__(1024) void k_classify(const Task* tasks, const uint
                 C.offset = 0;
             }
             next[s_tb + tidx[b]] = C;
+        }
+    }
+    // The other buckets of each group fold their min and max into the
+    // group's range, after the groups written above have reached memory
+    // (vmcnt counts this thread's stores; the barrier covers every thread's).
+    if (!over) {
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
+            if (kind[b] != kSmall)      // leaders carry kLead; other kinds form no group
+                continue;
+            const int32_t L = ldr[b];
+            if (L < 0)                  // a member always follows its leader
+                continue;
+            const int32_t e = nxt[f - 1 - L];
+            const uint64_t gsz = (e == kNone ? T.n : bst[e]) - bst[L];
+            const uint32_t c = gsz <= kGroupClassCap[0] ? 0u : (gsz <= kGroupClassCap[1] ? 1u : 2u);
+            Group* G = &groups.g[c][s_gb[c] + cidx[c][L]];
+            atomicMin(reinterpret_cast<unsigned long long*>(&G->lo),
+                      (unsigned long long)bstat[2 * ((uint64_t)T.bucket_off + b)]);
+            atomicMax(reinterpret_cast<unsigned long long*>(&G->hi),
+                      (unsigned long long)bstat[2 * ((uint64_t)T.bucket_off + b) + 1]);
         }
     }
     // Fill pieces, spread over the workgroup (one all-equal bucket of a
@@ -755,7 +784,7 @@ hipError_t launch_classify(const Task* d_tasks, uint32_t ntasks, const uint64_t*
 {
     if (!ntasks)
         return hipSuccess;
-    size_t smem = (size_t)(max_fanout + 1) * 8 + (size_t)max_fanout * (4 + 4 + 4 + 4 + 4 + 4 + 1) + 64;
+    size_t smem = (size_t)(max_fanout + 1) * 8 + (size_t)max_fanout * (4 + 4 + 4 + 4 + 4 + 4 + 4 + 1) + 64;
     // a round with a few wide tasks (level 0) gets wide workgroups
     const uint32_t threads = (ntasks <= 64 && max_fanout >= 1024) ? 1024u : 256u;
     k_classify<<<ntasks, threads, smem, st>>>(d_tasks, d_pos, d_bstat, thresh, param_fanout, d_next, groups,
@@ -1108,6 +1137,8 @@ __global__ __launch_bounds__(1024) void k_seg_prepare(SegPrepare A)
             g.start = 0;
             g.n = (uint32_t)n;
             g.dtype = dt;
+            g.lo = ~0ull;   // range not known: the base case finds it
+            g.hi = 0;
             A.groups[cls][off[cls]] = g;
         }
         if (task) {
