@@ -292,7 +292,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                             if (mix) {
                                 const uint32_t e = start[sl + 1];
                                 uint32_t r = 0;
-                                for (uint32_t j = s0; j < e; ++j) {
+                                // two keys per step: their LDS reads are in flight together
+                                uint32_t j = s0;
+                                for (; j + 2 <= e; j += 2) {
+                                    const uint64_t v0 = stage[j], v1 = stage[j + 1];
+                                    r += (v0 < o[k]) | ((v0 == o[k]) & (j < p));
+                                    r += (v1 < o[k]) | ((v1 == o[k]) & (j + 1 < p));
+                                }
+                                if (j < e) {
                                     const uint64_t v = stage[j];
                                     r += (v < o[k]) | ((v == o[k]) & (j < p));
                                 }
