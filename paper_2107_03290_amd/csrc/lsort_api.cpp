@@ -850,8 +850,9 @@ ls_status finish_eager(ls_ctx* C, hipStream_t st, const Params& P, Prof& prof, u
     for (uint32_t c = 0; c < kGroupClasses; ++c)
         gl.g[c] = (Group*)C->groups[c].p;
     const double gkeys = (double)F.group_keys + (double)group0_keys;
-    if (prof.on) {
-        // timed one kernel class at a time
+    if (prof.on && (prof.only < 0 || prof.only == 5 || prof.only == 6)) {
+        // the base case or the fills are timed: one kernel class at a time
+        // (otherwise the classes overlap as in an unprofiled sort)
         prof.begin(5);
         for (uint32_t c = 0; c < kGroupClasses; ++c)
             HIPCHECK(C, launch_base(gl.g[c], F.ngroups[c], c, nullptr, st));
