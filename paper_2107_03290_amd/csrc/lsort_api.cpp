@@ -110,9 +110,6 @@ struct ls_ctx {
     uint64_t gen = 0;                    // bumped whenever a buffer is reallocated
     PinBuf gstage;                       // staging of the replays' uploads
     hipStream_t cap_stream = nullptr;    // capture only; replays run on the caller's stream
-    // finish: the base-case size classes run side by side
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     // the end of the context's last queued sort on the caller's stream:
     // sync, trim and destroy wait for this context's work, not the device's
     hipEvent_t ev_done = nullptr;
@@ -806,38 +803,16 @@ ls_status rounds_eager(ls_ctx* C, hipStream_t st, const Params& P, LayoutParams 
     return LS_OK;
 }
 
-// The base case over the three size classes and the fills.  Host-driven:
-// classes 1 and 2 on side streams forked from st and joined back, class 0
-// and the fills on st.  Graph mode (gctl): all on st, so that no event or
-// side stream of the context takes part in a capture.
+// The base case over the three size classes and the fills, one after
+// another on the sort's stream.  (Running classes 1 and 2 on side streams
+// forked from it and joined back was slower on every workload measured: the
+// cross-stream waits cost more than the overlap gained.)
 ls_status launch_finish_lists(ls_ctx* C, const GroupLists& gl, const uint32_t* ngroups, const Fill* fills,
                               uint32_t nfill, const RoundCtl* gctl, hipStream_t st)
 {
-    const bool fork = !gctl && !C->no_alloc &&
-                      ((ngroups[1] && ngroups[2]) || ((ngroups[1] || ngroups[2]) && (ngroups[0] || nfill)));
-    if (!fork) {
-        for (uint32_t c = 0; c < kGroupClasses; ++c)
-            HIPCHECK(C, launch_base(gl.g[c], ngroups[c], c, gctl, st));
-        HIPCHECK(C, launch_fill(fills, nfill, gctl, st));
-        return LS_OK;
-    }
-    if (!C->ev_fork) {
-        for (int i = 0; i < 2; ++i)
-            HIPCHECK(C, hipStreamCreateWithFlags(&C->side[i], hipStreamNonBlocking));
-        HIPCHECK(C, hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
-        for (int i = 0; i < 2; ++i)
-            HIPCHECK(C, hipEventCreateWithFlags(&C->ev_join[i], hipEventDisableTiming));
-    }
-    HIPCHECK(C, hipEventRecord(C->ev_fork, st));
-    for (uint32_t i = 0; i < 2; ++i) {
-        HIPCHECK(C, hipStreamWaitEvent(C->side[i], C->ev_fork, 0));
-        HIPCHECK(C, launch_base(gl.g[2 - i], ngroups[2 - i], 2 - i, gctl, C->side[i]));
-        HIPCHECK(C, hipEventRecord(C->ev_join[i], C->side[i]));
-    }
-    HIPCHECK(C, launch_base(gl.g[0], ngroups[0], 0, gctl, st));
+    for (uint32_t c = 0; c < kGroupClasses; ++c)
+        HIPCHECK(C, launch_base(gl.g[c], ngroups[c], c, gctl, st));
     HIPCHECK(C, launch_fill(fills, nfill, gctl, st));
-    for (int i = 0; i < 2; ++i)
-        HIPCHECK(C, hipStreamWaitEvent(st, C->ev_join[i], 0));
     return LS_OK;
 }
 
@@ -850,9 +825,8 @@ ls_status finish_eager(ls_ctx* C, hipStream_t st, const Params& P, Prof& prof, u
     for (uint32_t c = 0; c < kGroupClasses; ++c)
         gl.g[c] = (Group*)C->groups[c].p;
     const double gkeys = (double)F.group_keys + (double)group0_keys;
-    if (prof.on && (prof.only < 0 || prof.only == 5 || prof.only == 6)) {
-        // the base case or the fills are timed: one kernel class at a time
-        // (otherwise the classes overlap as in an unprofiled sort)
+    if (prof.on) {
+        // timed one kernel class at a time
         prof.begin(5);
         for (uint32_t c = 0; c < kGroupClasses; ++c)
             HIPCHECK(C, launch_base(gl.g[c], F.ngroups[c], c, nullptr, st));
@@ -1363,9 +1337,8 @@ ls_status wait_ctx(ls_ctx* C)
     if (C->done_pending)
         HIPCHECK(C, hipEventSynchronize(C->ev_done));
     C->done_pending = false;
-    for (hipStream_t s : {C->side[0], C->side[1], C->cap_stream})
-        if (s)
-            HIPCHECK(C, hipStreamSynchronize(s));
+    if (C->cap_stream)
+        HIPCHECK(C, hipStreamSynchronize(C->cap_stream));
     return LS_OK;
 }
 
@@ -1573,14 +1546,6 @@ ls_status ls_destroy(ls_ctx* C)
     drop_graphs(C, true);
     if (C->cap_stream)
         (void)hipStreamDestroy(C->cap_stream);
-    for (int i = 0; i < 2; ++i) {
-        if (C->side[i])
-            (void)hipStreamDestroy(C->side[i]);
-        if (C->ev_join[i])
-            (void)hipEventDestroy(C->ev_join[i]);
-    }
-    if (C->ev_fork)
-        (void)hipEventDestroy(C->ev_fork);
     if (C->ev_done)
         (void)hipEventDestroy(C->ev_done);
     delete C;
