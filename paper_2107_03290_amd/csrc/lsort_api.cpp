@@ -392,6 +392,16 @@ ls_status resolve(ls_ctx* C, const ls_params* p, Params& P)
     // automatic tile: the wide tile is taken only by rounds whose fanouts fit
     P.wide_max_fanout = 0;
     if (P.tile_wide) {
+        // the 12,288-key tile (32-bit cursors) where the model leaves room for it
+        const size_t fixed12 = scatter_lds_bytes32(kTile12, 0) + model_lds + 128 + 16;
+        const size_t f12 = C->lds_limit > fixed12 ? (C->lds_limit - fixed12) / 16 : 0;
+        if (f12 >= P.fanout) {
+            P.tile_wide = kTile12;
+            P.wide_max_fanout = (uint32_t)std::min<size_t>(f12, kMaxFanout);
+            return LS_OK;
+        }
+    }
+    if (P.tile_wide) {
         const size_t fixed = scatter_lds_bytes(P.tile_wide, 0) + model_lds + 128 + 16;
         P.wide_max_fanout = C->lds_limit > fixed ? (uint32_t)std::min<size_t>((C->lds_limit - fixed) / 24, kMaxFanout)
                                                  : 0u;

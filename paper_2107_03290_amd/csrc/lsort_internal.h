@@ -260,6 +260,16 @@ __host__ __device__ inline size_t scatter_lds_bytes(uint32_t tile, uint32_t fano
     return ((size_t)tile * 10 + (size_t)fanout * 24 + 15) & ~(size_t)15;
 }
 
+// The 12,288-key tile: 32-bit cursors (task-relative; taken only by rounds
+// of fewer than 2^31 keys) leave room for it when the model has at most 512
+// leaves, and its runs per bucket are half as long again as the 8192-key
+// tile's.
+constexpr uint32_t kTile12 = 12288;
+__host__ __device__ inline size_t scatter_lds_bytes32(uint32_t tile, uint32_t fanout)
+{
+    return ((size_t)tile * 10 + (size_t)fanout * 16 + 15) & ~(size_t)15;
+}
+
 // Keys per window within which consecutive small buckets are sorted as one
 // base-case group.
 constexpr uint32_t kGroupWindow = 512;

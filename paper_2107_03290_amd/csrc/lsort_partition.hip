@@ -312,7 +312,9 @@ __device__ void layout_device(Task* tasks, ModelJob* jobs, const LayoutParams& l
     const uint64_t nkeys = s_keys;
     // a large round scatters in wide tiles when its fanouts leave room in LDS
     const uint32_t tile =
-        lp.tile_wide && nkeys >= lp.wide_keys && s_maxf <= lp.wide_max_fanout ? lp.tile_wide : lp.tile;
+        lp.tile_wide && nkeys >= lp.wide_keys && s_maxf <= lp.wide_max_fanout &&
+                (lp.tile_wide != kTile12 || nkeys < (1ull << 31))
+            ? lp.tile_wide : lp.tile;
     // at most lp.target_chunks chunks; a small round gets about one chunk
     // per CU, of one to four tiles
     uint64_t chunk = (nkeys + lp.target_chunks - 1) / lp.target_chunks;
@@ -804,12 +806,15 @@ constexpr uint32_t kScatterThreads = 1024;
 // ranked and written.
 //
 // LDS: the staged tile (8 B keys), then per bucket the cursor and the tile's
-// write base (8 B each), the tile count and tile start (4 B each), then the
-// staged bucket numbers (2 B per key), then the model.
-struct ScatterLds {
+// write base (8 B each; 4 B in the 12,288-key tile, whose rounds hold fewer
+// than 2^31 keys, so task-relative positions fit), the tile count and tile
+// start (4 B each), then the staged bucket numbers (2 B per key), then the
+// model.  A cursor's top bit marks a bucket that is not moved.
+template <typename CT = uint64_t>
+struct ScatterLdsT {
     uint64_t* stage;
-    uint64_t* cur;
-    uint64_t* wbase;
+    CT* cur;
+    CT* wbase;
     uint32_t* tcnt;
     uint32_t* tstart;
     uint16_t* sb;
@@ -819,17 +824,19 @@ struct ScatterLds {
     // position in the task's count-ordered layout
     uint64_t* ls1;
 };
+using ScatterLds = ScatterLdsT<uint64_t>;
 
-__device__ __forceinline__ ScatterLds scatter_lds(unsigned char* smem, uint32_t tile, uint32_t f)
+template <typename CT = uint64_t>
+__device__ __forceinline__ ScatterLdsT<CT> scatter_lds(unsigned char* smem, uint32_t tile, uint32_t f)
 {
-    ScatterLds L;
+    ScatterLdsT<CT> L;
     L.stage = reinterpret_cast<uint64_t*>(smem);
-    L.cur = L.stage + tile;
+    L.cur = reinterpret_cast<CT*>(L.stage + tile);
     L.wbase = L.cur + f;
     L.tcnt = reinterpret_cast<uint32_t*>(L.wbase + f);
     L.tstart = L.tcnt + f;
     L.sb = reinterpret_cast<uint16_t*>(L.tstart + f);
-    L.model = smem + scatter_lds_bytes(tile, f);
+    L.model = smem + (sizeof(CT) == 8 ? scatter_lds_bytes(tile, f) : scatter_lds_bytes32(tile, f));
     return L;
 }
 
@@ -839,9 +846,9 @@ __device__ __forceinline__ ScatterLds scatter_lds(unsigned char* smem, uint32_t 
 // write loop needs none behind it: the next tile's ranking touches only the
 // counts and the cursors' skip bits, and everything the write loop reads is
 // rewritten only after the next tile's first barrier.
-template <uint32_t KPT, uint32_t DT, bool MSD, bool LS1 = false>
+template <uint32_t KPT, uint32_t DT, bool MSD, bool LS1 = false, typename CT = uint64_t>
 __device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, gptr<const uint64_t> src,
-                                             gptr<uint64_t> dst, uint32_t n, const ScatterLds& L,
+                                             gptr<uint64_t> dst, uint32_t n, const ScatterLdsT<CT>& L,
                                              uint32_t* wsum, uint32_t flags, gptr<uint64_t> spill = {})
 {
     constexpr uint32_t NT = kScatterThreads;
@@ -883,7 +890,7 @@ __device__ __forceinline__ void scatter_body(const Task& T, const SModel& M, gpt
             if (i < n) {
                 const uint32_t b = MSD ? msd_bucket<DT>(raw[u], shift, f)
                                        : model_bucket<DT>(M, raw[u], scale, offset, f, flags);
-                if (!(L.cur[b] & kSkipBit)) {
+                if (!(L.cur[b] & (CT(1) << (sizeof(CT) * 8 - 1)))) {
                     bk[u] = b;
                     rk[u] = atomicAdd(&L.tcnt[b], 1u);
                 }
@@ -958,6 +965,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, 
     }
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr uint32_t TILE = KPT * kScatterThreads;
+    using CT = typename std::conditional<KPT == 12, uint32_t, uint64_t>::type;
+    constexpr CT kSkip = CT(1) << (sizeof(CT) * 8 - 1);
     __shared__ uint32_t s_task;
     __shared__ uint32_t wsum[kScatterThreads / 64 + 1];
     if (threadIdx.x == 0)
@@ -968,11 +977,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, 
         return;
     const Task T = tasks[ti];
     const uint32_t f = T.fanout;
-    const ScatterLds L = scatter_lds(smem, TILE, f);
+    const ScatterLdsT<CT> L = scatter_lds<CT>(smem, TILE, f);
     const uint32_t lc = blockIdx.x - T.chunk0;
     for (uint32_t b = threadIdx.x; b < f; b += blockDim.x) {
-        const uint64_t c = pos[T.cnt_off + (uint64_t)b * T.nchunks + lc] - T.cnt_base;
-        L.cur[b] = skip[(uint64_t)T.bucket_off + b] ? (c | kSkipBit) : c;
+        const CT c = (CT)(pos[T.cnt_off + (uint64_t)b * T.nchunks + lc] - T.cnt_base);
+        L.cur[b] = skip[(uint64_t)T.bucket_off + b] ? (CT)(c | kSkip) : c;
         L.tcnt[b] = 0;
     }
     SModel M{};
@@ -985,11 +994,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(const Task* tasks, 
     const gptr<const uint64_t> src = as_global<const uint64_t>((T.src ? T.scratch : T.keys) + T.start + lo);
     const gptr<uint64_t> dst = as_global((T.src ? T.keys : T.scratch) + T.start);
     if (T.dtype == kF64) {
-        if (msd) scatter_body<KPT, kF64, true>(T, M, src, dst, n, L, wsum, flags);
-        else scatter_body<KPT, kF64, false>(T, M, src, dst, n, L, wsum, flags);
+        if (msd) scatter_body<KPT, kF64, true, false, CT>(T, M, src, dst, n, L, wsum, flags);
+        else scatter_body<KPT, kF64, false, false, CT>(T, M, src, dst, n, L, wsum, flags);
     } else {
-        if (msd) scatter_body<KPT, kU64, true>(T, M, src, dst, n, L, wsum, flags);
-        else scatter_body<KPT, kU64, false>(T, M, src, dst, n, L, wsum, flags);
+        if (msd) scatter_body<KPT, kU64, true, false, CT>(T, M, src, dst, n, L, wsum, flags);
+        else scatter_body<KPT, kU64, false, false, CT>(T, M, src, dst, n, L, wsum, flags);
     }
 }
 
@@ -1222,6 +1231,11 @@ hipError_t launch_scatter(const Task* d_tasks, uint32_t ntasks, uint32_t total_c
     case 4096:
         k_scatter<4><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,
                                                                   d_task_flags, flags, live);
+        break;
+    case kTile12:
+        k_scatter<12><<<total_chunks, kScatterThreads,
+                        scatter_lds_bytes32(tile, max_fanout) + model_lds_bytes(max_leaves), st>>>(
+            d_tasks, ntasks, chunk, d_models, d_pos, d_skip, d_task_flags, flags, live);
         break;
     case 8192:
         k_scatter<8><<<total_chunks, kScatterThreads, smem, st>>>(d_tasks, ntasks, chunk, d_models, d_pos, d_skip,

@@ -170,6 +170,23 @@ def test_wide_tile_rounds_match_the_definition(S):
         assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("name", ["zipf_f64", "mixed_u64"])
+def test_12288_key_tile_matches_the_definition(S, name):
+    # with at most 512 leaves the automatic tile of rounds of at least 2^25
+    # keys is 12,288 keys (32-bit cursors) up to fanout 1202, the most its LDS
+    # holds beside a 512-leaf model (12288 * 10 + 1202 * 16 + 21576 bytes);
+    # fanout 1300 keeps the smaller tiles
+    n = (1 << 25) + 54_321
+    a = (W.zipf_lognormal(n, seed=15, distinct=400_000) if name == "zipf_f64"
+         else W.mixed_u64(n, seed=16))
+    want = expected_sorted(a)
+    for kw in (dict(leaves=512), dict(leaves=512, fanout=1202), dict(leaves=256, fanout=1000),
+               dict(leaves=512, fanout=1300)):
+        print("12288-key tile %s n=%d params=%s" % (name, n, kw), flush=True)
+        got = gpu_sort(S, a, ls.params(**kw))
+        assert np.array_equal(got, want)
+
+
 def test_tile_that_does_not_fit_shrinks(S):
     # 8192- and 4096-key tiles with 4096 buckets and the 1024-leaf model need
     # more LDS than one workgroup has: the tile is halved until it fits
