@@ -205,7 +205,7 @@ def bench_segments(args, torch, ls):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator; no dataset)",
         "config": {"workload": "segments_%d_f64" % (off.size - 1), "keys": n, "fanout": best.fanout,
-                   "tile": best.tile or "auto (4096; 8192 in rounds of >= 2^25 keys)",
+                   "tile": best.tile or "auto (4096; 8192, or 12288 with <= 512 leaves, in rounds of >= 2^25 keys)",
                    "base_threshold": best.base_threshold, "autotune_s": t_tune},
         "plain": {"value": n / (ms_p / 1e3), "unit": "keys/s", "ms": ms_p,
                   "calls": int(off.size - 1), "params": "defaults"},
@@ -784,7 +784,7 @@ def main():
         "dtype": "f64" if keys.dtype == np.float64 else "u64",
         "data": "synthetic (seeded generator; no dataset)",
         "config": {"workload": wname, "n": n, "fanout": p.fanout, "leaves": p.leaves,
-                   "tile": p.tile or "auto (4096; 8192 in rounds of >= 2^25 keys)",
+                   "tile": p.tile or "auto (4096; 8192, or 12288 with <= 512 leaves, in rounds of >= 2^25 keys)",
                    "base_threshold": p.base_threshold, "sample_rate": p.sample_rate, "sample_cap": p.sample_cap},
         "roofline": roof,
         "kernel_ms_per_step": breakdown,

@@ -81,7 +81,9 @@ typedef struct {
                                   (halved down to 1024 while the tile, the fanout's tables and the model
                                   exceed a workgroup's LDS), or 0 (ls_default_params) for automatic: 4096,
                                   and 8192 in host-driven rounds of at least 2^25 keys whose fanouts leave
-                                  room for it in LDS */
+                                  room for it in LDS; 12288 instead (32-bit cursors) in such rounds of
+                                  fewer than 2^31 keys when leaves <= 512 and the fanouts fit (at most
+                                  1202 with 512 leaves) */
     uint32_t base_threshold;   /* buckets of at most this many keys are sorted in LDS, in groups of < 2x (default 4096, max 4096) */
     uint32_t flags;            /* LS_FLAG_* */
     double   sample_rate;      /* model training sample (default 0.01) */
